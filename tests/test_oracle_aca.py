@@ -1,0 +1,85 @@
+"""Pins of the oracle ACA, Algorithm 2 with 3x3 entries (CPU only).
+
+A block that is exactly a sum of r separable 3x3 terms is recovered with rank
+r; with zero tolerance ACA interpolates the full block; after every step the
+residual vanishes on the chosen rows and columns; the incremental nu^2 and
+lambda^2 equal brute-force Frobenius norms; on admissible RPY and MLP blocks
+the block error stays within 10 zeta.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import aca, kernels, partition, tree
+
+
+def _sep_block(c, q, r, seed):
+    rng = wl.Rng(seed, "misc")
+    A = rng.normal(r * c * 9).reshape(r, c, 3, 3)
+    B = rng.normal(r * q * 9).reshape(r, q, 3, 3)
+    G = np.einsum("sIab,sJbc->IJac", A, B)
+    return G
+
+
+@pytest.mark.parametrize("r", [1, 2, 5])
+def test_exact_rank_recovered(r):
+    c, q = 40, 33
+    G = _sep_block(c, q, r, 30 + r)
+    res = aca.aca_entries(lambda j: G[:, j], lambda i: G[i, :], c, q, 1e-10, 20)
+    assert res.converged
+    assert res.rank in (r, r + 1)
+    err = np.linalg.norm(aca.lowrank_dense(res) - G) / np.linalg.norm(G)
+    assert err < 1e-12
+
+
+def _rpy_block(seed=0):
+    X = wl.rsa_cube(2000, 0.1, seed=seed)
+    tr = tree.build_tree(X, 64)
+    G, _ = partition.build_partition(tr, 1.0)
+    Xs = X[tr.perm]
+    out = []
+    for t, s in G[:: max(1, len(G) // 12)]:
+        out.append((Xs[tr.nodes[t, 0]:tr.nodes[t, 1]], Xs[tr.nodes[s, 0]:tr.nodes[s, 1]]))
+    return out
+
+
+def test_zero_tolerance_interpolates_block():
+    kern = kernels.Kernel("rpy")
+    Xt, Xs = _rpy_block()[0]
+    Xt, Xs = Xt[:12], Xs[:9]
+    res = aca.aca_block(kern, Xt, Xs, 0.0, 100)
+    G = kern(Xt[:, None] - Xs[None])
+    assert res.converged and res.rank == 9
+    assert np.linalg.norm(aca.lowrank_dense(res) - G) <= 1e-10 * np.linalg.norm(G)
+
+
+def test_residual_zero_on_pivots_and_norms_match():
+    kern = kernels.Kernel("rpy")
+    Xt, Xs = _rpy_block()[3]
+    G = kern(Xt[:, None] - Xs[None])
+    res = aca.aca_block(kern, Xt, Xs, 1e-8, 30)
+    gnorm = np.linalg.norm(G)
+    for k in range(1, res.rank + 1):
+        approx = np.einsum("kiab,kjbc->ijac", res.C[:k], res.Q[:k])
+        E = G - approx
+        for m in range(k):
+            assert np.linalg.norm(E[res.piv_i[m]]) <= 1e-11 * gnorm
+            assert np.linalg.norm(E[:, res.piv_j[m]]) <= 1e-11 * gnorm
+        term = np.einsum("iab,jbc->ijac", res.C[k - 1], res.Q[k - 1])
+        assert res.nu2[k - 1] == pytest.approx(np.sum(term * term), rel=1e-10)
+        assert res.lam2[k - 1] == pytest.approx(np.sum(approx * approx), rel=1e-10)
+
+
+@pytest.mark.parametrize("kind,eps", [("rpy", 1e-4), ("rpy", 1e-6), ("mlp", 1e-4)])
+def test_block_error_within_ten_zeta(kind, eps):
+    if kind == "rpy":
+        kern = kernels.Kernel("rpy")
+    else:
+        Ws, bs = wl.mlp_weights(1)
+        kern = kernels.Kernel("mlp", kernels.MLP(Ws, bs))
+    for Xt, Xs in _rpy_block(1):
+        G = kern(Xt[:, None] - Xs[None])
+        res = aca.aca_block(kern, Xt, Xs, eps, 48)
+        assert res.converged
+        err = np.linalg.norm(aca.lowrank_dense(res) - G) / np.linalg.norm(G)
+        assert err <= 10 * eps

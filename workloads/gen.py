@@ -1,0 +1,345 @@
+"""Seeded generators for particle configurations, forces and kernel weights.
+
+Every random number comes from numpy's PCG64 bit generator as raw 64-bit words
+(a stream that numpy keeps stable across versions) and is mapped to uniforms
+and normals here, so the values do not depend on numpy's distribution code.
+
+Workload recipes follow the paper's synthetic set-ups: spheres of radius a=1 in
+an unbounded fluid (Sec. 2.1), perturbed primitive cubic lattices (Sec. 4.1),
+spherical suspension drops built as lattice points inside a ball and then
+jittered, under gravity-like forces F=(0,0,-1) (Sec. 4.3.1), and bead chains
+for flexible filaments (Sec. 4.3.2).
+"""
+from __future__ import annotations
+
+import math
+import os
+
+import numpy as np
+from scipy.spatial import cKDTree
+
+_STREAMS = {"pos": 0, "force": 1, "weights": 2, "rows": 3, "fd": 4, "sizes": 5,
+            "kinds": 6, "phi": 7, "chain": 8, "w": 9, "misc": 10}
+
+
+class Rng:
+    """Counter-free wrapper around PCG64 raw output with explicit mappings."""
+
+    def __init__(self, seed: int, stream: str | int = 0):
+        sid = _STREAMS[stream] if isinstance(stream, str) else int(stream)
+        ss = np.random.SeedSequence([int(seed), sid])
+        self._bg = np.random.PCG64(ss)
+
+    def raw(self, n: int) -> np.ndarray:
+        return self._bg.random_raw(int(n)).astype(np.uint64)
+
+    def uniform(self, n: int) -> np.ndarray:
+        """Doubles in [0, 1) with 53 random bits each."""
+        return (self.raw(n) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+    def uniform_pm(self, n: int, half: float) -> np.ndarray:
+        return (2.0 * self.uniform(n) - 1.0) * half
+
+    def normal(self, n: int) -> np.ndarray:
+        """Standard normals by the Box-Muller transform (pairs of uniforms)."""
+        m = (int(n) + 1) // 2
+        u1 = 1.0 - self.uniform(m)          # (0, 1]
+        u2 = self.uniform(m)
+        rad = np.sqrt(-2.0 * np.log(u1))
+        z = np.empty(2 * m)
+        z[0::2] = rad * np.cos(2.0 * np.pi * u2)
+        z[1::2] = rad * np.sin(2.0 * np.pi * u2)
+        return z[: int(n)]
+
+
+def cube_side(n: int, phi: float, a: float = 1.0) -> float:
+    """Side of the cube holding n spheres of radius a at volume fraction phi."""
+    return a * (4.0 * math.pi * n / (3.0 * phi)) ** (1.0 / 3.0)
+
+
+def drop_radius(n: int, phi: float, a: float = 1.0) -> float:
+    return a * (n / phi) ** (1.0 / 3.0)
+
+
+def _cached(name, fn):
+    """Memoise a generated array in a local directory (inputs are deterministic)."""
+    d = os.environ.get("HH_INPUT_CACHE", "/tmp/hh_inputs")
+    path = os.path.join(d, name + ".npy")
+    try:
+        return np.load(path)
+    except (OSError, ValueError):
+        pass
+    arr = fn()
+    try:
+        os.makedirs(d, exist_ok=True)
+        tmp = path + ".%d.tmp" % os.getpid()
+        with open(tmp, "wb") as f:
+            np.save(f, arr)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+    return arr
+
+
+def rsa_cube(n: int, phi: float, min_dist: float = 2.05, a: float = 1.0,
+             seed: int = 0, batch: int = 4096) -> np.ndarray:
+    """Cached front end of _rsa_cube (see there)."""
+    key = "rsa_n%d_phi%.6g_d%.6g_a%.6g_s%d_b%d" % (n, phi, min_dist, a, seed, batch)
+    if n < 20000:
+        return _rsa_cube(n, phi, min_dist, a, seed, batch)
+    return _cached(key, lambda: _rsa_cube(n, phi, min_dist, a, seed, batch))
+
+
+def _rsa_cube(n: int, phi: float, min_dist: float = 2.05, a: float = 1.0,
+              seed: int = 0, batch: int = 4096) -> np.ndarray:
+    """Random sequential addition of n centres uniform in [0, L)^3.
+
+    A candidate is accepted when its distance to every earlier accepted centre
+    is at least min_dist. Candidates are drawn in batches, but the acceptance
+    decision is exactly the sequential one in draw order.
+    """
+    n = int(n)
+    L = cube_side(n, phi, a)
+    rng = Rng(seed, "pos")
+    nc = max(1, int(math.floor(L / min_dist)))
+    w = L / nc
+    slots = 8
+    grid = np.full((nc, nc, nc, slots), -1, dtype=np.int64)
+    fill = np.zeros((nc, nc, nc), dtype=np.int64)
+    pos = np.empty((n, 3))
+    count = 0
+    d2min = min_dist * min_dist
+    offs = np.array([(i, j, k) for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)])
+    tries = 0
+    while count < n:
+        tries += 1
+        if tries > 100000:
+            raise RuntimeError("rsa_cube: volume fraction too high to place spheres")
+        cand = rng.uniform(3 * batch).reshape(batch, 3) * L
+        cell = np.minimum((cand / w).astype(np.int64), nc - 1)
+        nb = cell[:, None, :] + offs[None, :, :]                       # [B,27,3]
+        ok_cell = np.all((nb >= 0) & (nb < nc), axis=2)
+        nbc = np.clip(nb, 0, nc - 1)
+        idx = grid[nbc[..., 0], nbc[..., 1], nbc[..., 2]]              # [B,27,slots]
+        idx = np.where(ok_cell[..., None], idx, -1).reshape(batch, -1)
+        valid = idx >= 0
+        p = pos[np.where(valid, idx, 0)]
+        d2 = np.sum((p - cand[:, None, :]) ** 2, axis=2)
+        clash = np.any(valid & (d2 < d2min), axis=1)
+        surv = np.nonzero(~clash)[0]
+        if surv.size:
+            cs = cand[surv]
+            pairs = cKDTree(cs).query_pairs(min_dist, output_type="ndarray")
+            if pairs.size:   # drop pairs at exactly min_dist (allowed)
+                dp = cs[pairs[:, 0]] - cs[pairs[:, 1]]
+                pairs = pairs[np.sum(dp * dp, axis=1) < d2min]
+            acc_mask = np.ones(surv.size, dtype=bool)
+            if pairs.size:
+                # only candidates that clash with another batch member need the
+                # sequential rule: accepted iff no earlier accepted member clashes
+                earlier = {}
+                for u, v in pairs.tolist():
+                    lo_, hi_ = (u, v) if u < v else (v, u)
+                    earlier.setdefault(hi_, []).append(lo_)
+                for t in sorted(set(earlier) | {u for lst in earlier.values() for u in lst}):
+                    acc_mask[t] = not any(acc_mask[u] for u in earlier.get(t, ()))
+            accepted = np.nonzero(acc_mask)[0][: n - count]
+            for t in accepted:
+                c = cell[surv[t]]
+                f = fill[c[0], c[1], c[2]]
+                if f >= slots:
+                    raise RuntimeError("rsa_cube: cell overflow")
+                grid[c[0], c[1], c[2], f] = count
+                fill[c[0], c[1], c[2]] = f + 1
+                pos[count] = cs[t]
+                count += 1
+    return pos
+
+
+def lattice_sphere(n: int, phi: float, jitter: float = 0.25, a: float = 1.0,
+                   seed: int = 0) -> np.ndarray:
+    """n points of a primitive cubic lattice nearest the centre, then jittered.
+
+    Lattice spacing s = a (4 pi / (3 phi))^(1/3) gives volume fraction phi.
+    Points are ranked by squared integer distance from the centre with a
+    lexicographic tie-break, and each coordinate is then moved by U(-jitter a,
+    jitter a), which keeps centres at least s - 2 sqrt(3) jitter a apart.
+    """
+    n = int(n)
+    s = a * (4.0 * math.pi / (3.0 * phi)) ** (1.0 / 3.0)
+    m = int(math.ceil((3.0 * n / (4.0 * math.pi)) ** (1.0 / 3.0))) + 2
+    r = np.arange(-m, m + 1, dtype=np.int64)
+    I, J, K = np.meshgrid(r, r, r, indexing="ij")
+    I, J, K = I.ravel(), J.ravel(), K.ravel()
+    d2 = I * I + J * J + K * K
+    order = np.lexsort((K, J, I, d2))[:n]
+    pts = np.stack([I[order], J[order], K[order]], axis=1).astype(np.float64) * s
+    del I, J, K, d2, order
+    rng = Rng(seed, "pos")
+    pts += rng.uniform_pm(3 * n, jitter * a).reshape(n, 3)
+    return pts
+
+
+def normal_forces(n: int, seed: int = 0, scale: float = 1.0,
+                  dtype=np.float64) -> np.ndarray:
+    """F_i ~ N(0, scale^2 I3)."""
+    rng = Rng(seed, "force")
+    return (scale * rng.normal(3 * int(n)).reshape(int(n), 3)).astype(dtype)
+
+
+def gravity_forces(n: int, seed: int = 0, var: float = 0.1,
+                   dtype=np.float64) -> np.ndarray:
+    """F_i = (0, 0, -1) + N(0, var I3)."""
+    f = normal_forces(n, seed, math.sqrt(var))
+    f[:, 2] -= 1.0
+    return f.astype(dtype)
+
+
+def mlp_weights(seed: int = 1, widths=(3, 64, 64, 64, 9)):
+    """Glorot-uniform weights W[out][in] ~ U(+-sqrt(6/(in+out))), biases
+    b ~ U(+-1/sqrt(in)), drawn in the order W1, b1, W2, b2, ... from one stream."""
+    rng = Rng(seed, "weights")
+    Ws, bs = [], []
+    for fin, fout in zip(widths[:-1], widths[1:]):
+        lim = math.sqrt(6.0 / (fin + fout))
+        Ws.append(rng.uniform_pm(fout * fin, lim).reshape(fout, fin))
+        bs.append(rng.uniform_pm(fout, 1.0 / math.sqrt(fin)))
+    return Ws, bs
+
+
+def sample_rows(n: int, k: int, seed: int = 3) -> np.ndarray:
+    """k distinct row indices of [0, n), uniform without replacement, ascending."""
+    rng = Rng(seed, "rows")
+    keys = rng.raw(int(n))
+    pick = np.argsort(keys, kind="stable")[: int(k)]
+    return np.sort(pick).astype(np.int64)
+
+
+def _rotate_bond(prev: np.ndarray, theta: float, psi: float) -> np.ndarray:
+    """Unit vector at polar angle theta from prev, azimuth psi around it."""
+    t = prev / np.linalg.norm(prev)
+    helper = np.array([1.0, 0.0, 0.0]) if abs(t[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    u = np.cross(t, helper)
+    u /= np.linalg.norm(u)
+    v = np.cross(t, u)
+    return math.cos(theta) * t + math.sin(theta) * (math.cos(psi) * u + math.sin(psi) * v)
+
+
+def filament_system(n: int, phi: float, beads: int = 50, bond: float = 2.2,
+                    bend_sd: float = 0.3, min_dist: float = 2.05, a: float = 1.0,
+                    seed: int = 0, max_tries: int = 100) -> np.ndarray:
+    """Chains of `beads` beads (n rounded down to a multiple of beads).
+
+    Each chain starts at a uniform point of the cube sized for phi; each bond has
+    length `bond` and turns from the previous bond by a polar angle |theta|,
+    theta ~ N(0, bend_sd), with uniform azimuth. A bead closer than min_dist to
+    any earlier non-adjacent bead is redrawn (up to max_tries times).
+    """
+    nchain = int(n) // beads
+    n = nchain * beads
+    L = cube_side(n, phi, a)
+    rng = Rng(seed, "chain")
+    pos = np.empty((n, 3))
+    nc = max(1, int(math.floor(L / min_dist)))
+    w = L / nc
+    cells: dict = {}
+    d2min = min_dist * min_dist
+
+    def clash(p, skip):
+        c = np.floor(p / w).astype(np.int64)
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dz in (-1, 0, 1):
+                    lst = cells.get((int(c[0] + dx), int(c[1] + dy), int(c[2] + dz)))
+                    if not lst:
+                        continue
+                    for q in lst:
+                        if q == skip:
+                            continue
+                        d = pos[q] - p
+                        if d @ d < d2min:
+                            return True
+        return False
+
+    def add(idx, p):
+        c = np.floor(p / w).astype(np.int64)
+        cells.setdefault((int(c[0]), int(c[1]), int(c[2])), []).append(idx)
+
+    k = 0
+    for _ in range(nchain):
+        for attempt in range(10 * max_tries):
+            p = rng.uniform(3) * L
+            if not clash(p, -1):
+                break
+        pos[k] = p
+        add(k, p)
+        k += 1
+        d = rng.normal(3)
+        d /= np.linalg.norm(d)
+        for _b in range(1, beads):
+            for attempt in range(max_tries):
+                th = abs(float(rng.normal(1)[0])) * bend_sd
+                ps = float(rng.uniform(1)[0]) * 2.0 * math.pi
+                nd = _rotate_bond(d, th, ps)
+                p = pos[k - 1] + bond * a * nd
+                if not clash(p, k - 1):
+                    break
+            d = nd
+            pos[k] = p
+            add(k, p)
+            k += 1
+    return pos
+
+
+def batch_systems(n_sys: int = 64, nmin: int = 5000, nmax: int = 200000, seed: int = 2):
+    """Per-system sizes (log-uniform in [nmin, nmax]), kinds and volume fractions.
+
+    Even-numbered systems are free spheres, odd-numbered ones are filaments.
+    Returns a list of dicts {n, kind, phi, seed}.
+    """
+    rs = Rng(seed, "sizes")
+    u = rs.uniform(n_sys)
+    sizes = np.floor(np.exp(math.log(nmin) + u * (math.log(nmax) - math.log(nmin)))).astype(np.int64)
+    rp = Rng(seed, "phi")
+    phis = 0.05 + 0.25 * rp.uniform(n_sys)
+    out = []
+    for s in range(n_sys):
+        kind = "spheres" if s % 2 == 0 else "filaments"
+        n = int(sizes[s])
+        if kind == "filaments":
+            n = max(50, (n // 50) * 50)
+        out.append({"n": n, "kind": kind, "phi": float(phis[s]), "seed": 1000 + s})
+    return out
+
+
+# Named workloads (positions generator, forces, kernel, H-matrix parameters).
+WORKLOADS = {
+    "plain_small": dict(n=2000, geom="cube", phi=0.10, seed=0, forces="normal",
+                        kernel="rpy", precision="fp64", c_leaf=64, eta=1.0, eps=1e-6),
+    "plain_fp32": dict(n=100000, geom="cube", phi=0.20, seed=0, forces="normal",
+                       kernel="mlp", precision="fp32", c_leaf=128, eta=1.0, eps=1e-4),
+    "precision_1m": dict(n=1000000, geom="sphere", phi=0.10, seed=0, forces="gravity",
+                         kernel="mlp", precision="bf16", c_leaf=128, eta=1.0, eps=1e-4),
+    "precision_10m": dict(n=10000000, geom="sphere", phi=0.10, seed=0, forces="gravity",
+                          kernel="mlp", precision="bf16", c_leaf=128, eta=1.0, eps=1e-4),
+    "diff_200k": dict(n=200000, geom="cube", phi=0.15, seed=0, forces="normal",
+                      kernel="mlp", precision="fp32", c_leaf=128, eta=1.0, eps=1e-4),
+    "diff_5k": dict(n=5000, geom="cube", phi=0.15, seed=0, forces="normal",
+                    kernel="mlp", precision="fp32", c_leaf=128, eta=1.0, eps=1e-4),
+}
+
+
+def workload(name: str, n: int | None = None):
+    """Positions and forces of a named workload (optionally at another n)."""
+    w = dict(WORKLOADS[name])
+    if n is not None:
+        w["n"] = int(n)
+    if w["geom"] == "cube":
+        X = rsa_cube(w["n"], w["phi"], seed=w["seed"])
+    else:
+        X = lattice_sphere(w["n"], w["phi"], seed=w["seed"])
+    if w["forces"] == "normal":
+        F = normal_forces(w["n"], seed=w["seed"])
+    else:
+        F = gravity_forces(w["n"], seed=w["seed"])
+    return X, F, w
