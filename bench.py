@@ -1,0 +1,185 @@
+"""Benchmark of one H-matrix mobility step U = M(X) F on one MI355X.
+
+A step is the whole hot path on one configuration: cluster tree, block
+partition, ACA of every admissible block, and the product (near field, far
+field, self term, unpermute) -- the paper rebuilds the H-matrix every time
+step because X moves (Secs. 3, 4.3). Inputs are synthetic and seeded
+(workloads/), resident in HBM before the timed region.
+
+Prints ONE JSON line (rank 0). The roofline object is for the dominant kernel
+(largest device time per step), with its average launch duration measured
+live with HIP events on the library's stream; the cpu_baseline object is the
+plain FP64 CPU oracle on a time-bounded sample of rows of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK = {"hbm_GBs": 8000.0, "bf16_TFs": 2500.0, "fp32_TFs": 157.3, "fp64_TFs": 78.6}
+MLP_MAC = 3 * 64 + 64 * 64 + 64 * 64 + 64 * 9      # 8,960 multiply-adds per kernel query
+MLP_FLOP = 2 * MLP_MAC
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="precision_1m")
+    ap.add_argument("--n", type=int, default=None, help="override the workload's N")
+    ap.add_argument("--prec", default=None, help="override precision (fp64, fp32, bf16)")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--l-max", type=int, default=48)
+    return ap.parse_args()
+
+
+def cpu_baseline(X, F, kern_cfg, U_gpu, budget_s):
+    """The FP64 dense oracle on sampled rows, bounded by budget_s seconds."""
+    import workloads as wl
+    from oracle import dense as OD
+    from oracle import kernels as OK
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    if kern_cfg["kernel"] == "rpy":
+        ko = OK.Kernel("rpy")
+    else:
+        ko = OK.Kernel("mlp", OK.MLP(*wl.mlp_weights(1)))
+    n = X.shape[0]
+    rows = wl.sample_rows(n, 256, seed=3)
+    got, t0 = [], time.perf_counter()
+    ref = []
+    for r in rows:
+        ref.append(OD.dense_u(X, F, ko, np.array([r]))[0])
+        got.append(r)
+        if time.perf_counter() - t0 > budget_s and len(got) >= 4:
+            break
+    dt = time.perf_counter() - t0
+    ref = np.array(ref)
+    g = np.asarray(got)
+    err = float(np.linalg.norm(U_gpu[g] - ref) / np.linalg.norm(ref))
+    return {"value": len(g) / dt, "unit": "particles/s", "cores": int(threads), "kind": "oracle",
+            "sample": "%d sampled rows (seed 3) of the dense FP64 sum over all %d sources, "
+                      "%.1f s" % (len(g), n, dt)}, err, len(g)
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2505_08174_amd as hh
+    import workloads as wl
+
+    X, F, cfg = wl.workload(a.workload, a.n)
+    prec = a.prec or cfg["precision"]
+    n = X.shape[0]
+    log("workload %s n=%d prec=%s" % (a.workload, n, prec))
+    ctx = hh.Context(0)
+    if cfg["kernel"] == "rpy":
+        kern = hh.Kernel.rpy(ctx)
+    else:
+        kern = hh.Kernel.mlp(ctx, wl.mlp_weights(1), "direction")
+    fdt = torch.float64 if prec == "fp64" else torch.float32
+    Xd = torch.tensor(X, dtype=torch.float64, device="cuda:0")
+    Fd = torch.tensor(F, dtype=fdt, device="cuda:0")
+    torch.cuda.synchronize()
+
+    def step():
+        t = hh.build_tree(ctx, Xd, cfg["c_leaf"])
+        p = hh.partition(ctx, t, cfg["eta"])
+        lr = hh.aca_build(ctx, t, p, kern, prec, cfg["eps"], a.l_max)
+        U = hh.matvec(ctx, t, p, lr, kern, Fd, prec)
+        return U, t, p, lr
+
+    for i in range(a.warmup):
+        U, t, p, lr = step()
+        torch.cuda.synchronize()
+        log("warmup %d done" % i)
+    ctx.set_profiling(True)
+    ctx.phase_times(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        U, t, p, lr = step()
+        log("step %d enqueued" % i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ph = ctx.phase_times(reset=True)
+    ctx.set_profiling(False)
+    ms = (t1 - t0) * 1e3 / a.steps
+    U_host = U.double().cpu().numpy()
+    nn, nl = t.info()[1:]
+    nG, nH = p.info()
+    ps = p.stats()
+    li = lr.info()
+    pairs_near = ps["near_pairs"] - n          # self pairs are skipped
+    per_step = {k: v[0] / a.steps for k, v in ph.items()}
+    log("phases ms/step:", {k: round(v, 3) for k, v in per_step.items()})
+    # dominant kernel
+    dom = max(("near", "aca"), key=lambda k: per_step[k])
+    if dom == "near":
+        flop = pairs_near * MLP_FLOP if cfg["kernel"] == "mlp" else pairs_near * 40
+        launch_ms = ph["near"][0] / max(1, ph["near"][1])
+    else:
+        flop = li["samples"] * MLP_FLOP if cfg["kernel"] == "mlp" else li["samples"] * 40
+        launch_ms = ph["aca"][0] / max(1, ph["aca"][1])
+    achieved = flop / (launch_ms * 1e-3) / 1e12
+    if prec == "bf16":
+        bound, peak = "mfma", PEAK["bf16_TFs"]
+    elif prec == "fp32":
+        bound, peak = "alu", PEAK["fp32_TFs"]
+    else:
+        bound, peak = "alu", PEAK["fp64_TFs"]
+    roof = {"bound": bound, "kernel": "k_near" if dom == "near" else "k_aca",
+            "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 5), "traffic": None,
+            "launch_ms": round(launch_ms, 4), "algorithmic_flop_per_launch": flop}
+    out = {
+        "metric": "H-matvec ms/step and particles/s at N=1M, rel err vs FP64 dense; MFMA%, HBM GB/s",
+        "value": n / (ms * 1e-3), "unit": "particles/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32",
+                                                         "bf16": "bf16"}[prec],
+        "data": "synthetic",
+        "config": {"workload": a.workload, "n": n, "kernel": cfg["kernel"], "precision": prec,
+                   "c_leaf": cfg["c_leaf"], "eta": cfg["eta"], "eps": cfg["eps"],
+                   "l_max": a.l_max, "geometry": cfg["geom"], "phi": cfg["phi"]},
+        "phases_ms": {k: round(v, 3) for k, v in per_step.items()},
+        "work": {"nodes": nn, "leaves": nl, "blocks_G": nG, "blocks_H": nH,
+                 "near_pairs": pairs_near, "aca_samples": li["samples"],
+                 "rank_sum": li["rank_sum"], "fallbacks": li["n_fallback"],
+                 "factor_bytes": li["bytes"]},
+        "roofline": roof,
+    }
+    if not a.no_cpu:
+        cb, err, nrows = cpu_baseline(X, F, cfg, U_host, a.cpu_seconds)
+        out["cpu_baseline"] = cb
+        out["eps_r_sampled_rows"] = err
+        out["eps_r_rows"] = nrows
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,228 @@
+/*
+ * hh.h -- C ABI of the MI355X H-matrix mobility library.
+ *
+ * The library computes the per-time-step hot path of an H-matrix accelerated
+ * hydrodynamic-interaction surrogate (arXiv 2505.08174, Sec. 3):
+ *
+ *     U = M(X) F,   U_i = alpha_1 F_i + sum_{j != i} K(x_i - x_j) F_j      (1)
+ *
+ * for N spheres at positions X (Eq. (2) restricted to the one-body term and
+ * the two-body off-diagonal term, i.e. M^(1) F + M^(t,2) F of Eq. (6)). Every
+ * matrix entry is a 3x3 block (Sec. 3, footnote). The dense two-body matrix is
+ * replaced by an H-matrix: a geometric cluster tree (Definition 1, Fig. 2), a
+ * block partition by the admissibility test Eq. (7) (Algorithm 1), adaptive
+ * cross approximation of admissible blocks (Eqs. (8)-(10), Algorithm 2), a
+ * dense on-the-fly evaluation of inadmissible leaf blocks, and the low-rank
+ * product C (Q F) (Sec. 3).
+ *
+ * Conventions shared by every entry point
+ *  - Arrays named "device" are HIP device pointers owned by the caller and
+ *    borrowed for the duration of the enqueued work. Arrays named "host" are
+ *    ordinary host memory; calls that read or write host arrays synchronise
+ *    the context stream before returning.
+ *  - Positions X are FP64, row-major [N][3], in the caller's particle order.
+ *    Forces and velocities are row-major [N][3] in the caller's order, with
+ *    the element type fixed by the precision (see hh_precision).
+ *  - Displacements are r = x_i - x_j (target minus source).
+ *  - Every call enqueues on the context's HIP stream. Calls noted "syncs"
+ *    also wait for the stream (they read back list sizes to size storage).
+ *  - Handles (tree, partition, low-rank factors, kernel) are owned by the
+ *    library and released by the matching *_free; freeing NULL is a no-op.
+ *    A handle must not outlive the context that made it.
+ *  - Errors: every call returns an hh_status; hh_last_error() gives a text
+ *    for the last failing call on that context. Nothing throws across the ABI.
+ *    On error, output handles are set to NULL and nothing is leaked.
+ *  - One context per host thread and stream; contexts are independent.
+ */
+#ifndef HH_H
+#define HH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hh_ctx_s* hh_ctx;
+typedef struct hh_tree_s* hh_tree;
+typedef struct hh_part_s* hh_part;
+typedef struct hh_lowrank_s* hh_lowrank;
+typedef struct hh_kernel_s* hh_kernel;
+
+typedef enum {
+  HH_OK = 0,
+  HH_ERR_INVALID_ARG = 1,      /* a size, pointer or parameter is out of range */
+  HH_ERR_OUT_OF_MEMORY = 2,    /* device allocation failed */
+  HH_ERR_HIP = 3,              /* a HIP runtime call failed */
+  HH_ERR_DUPLICATE_POINTS = 4, /* two particles coincide: K is singular at r=0 */
+  HH_ERR_CAPACITY = 5,         /* an internal list exceeded its bound */
+  HH_ERR_NOT_CONVERGED = 6     /* ACA did not converge and fallback is off */
+} hh_status;
+
+/* Arithmetic of the kernel evaluation, factors and sums.
+ *   HH_FP64 : F, U, factors and all sums in FP64.
+ *   HH_FP32 : F, U, kernel evaluation, factors and sums in FP32.
+ *   HH_BF16 : seeded-MLP layers in BF16 on MFMA with FP32 accumulation; ACA
+ *             pivot selection and stopping norms in FP64; factors FP32; the
+ *             final velocity sum in FP64. F is FP32 and U is FP64. */
+typedef enum { HH_FP64 = 0, HH_FP32 = 1, HH_BF16 = 2 } hh_precision;
+
+/* Input of the seeded MLP kernel: the unit direction r/|r| (default; gives
+ * an asymptotically smooth kernel, the premise of the low-rank step at the
+ * end of Sec. 3.1) or the raw displacement r. */
+typedef enum { HH_MLP_INPUT_DIRECTION = 0, HH_MLP_INPUT_DISPLACEMENT = 1 } hh_mlp_input;
+
+/* Size of the packed MLP parameter vector: W1[64][3] b1[64] W2[64][64] b2[64]
+ * W3[64][64] b3[64] W4[9][64] b4[9], each row-major [out][in]. */
+#define HH_MLP_NPARAM 9161
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device` that enqueues on `stream`
+ * (a hipStream_t; NULL = the null stream). */
+hh_status hh_ctx_create(int device, void* stream, hh_ctx* out);
+void hh_ctx_destroy(hh_ctx ctx);
+const char* hh_last_error(hh_ctx ctx);
+/* Replace the stream used by later calls. */
+hh_status hh_ctx_set_stream(hh_ctx ctx, void* stream);
+/* Device memory (bytes) that ACA factors may occupy. When the factors of all
+ * admissible blocks would not fit in half of it, hh_aca_build only plans
+ * and hh_matvec builds and applies them in batches of blocks whose factors
+ * fit (a fixed buffer filled, applied and reused, Sec. 3.3.2). The default is
+ * 40% of the free device memory at context creation. */
+hh_status hh_ctx_set_budget(hh_ctx ctx, size_t bytes);
+/* Wait for all work enqueued by this context. */
+hh_status hh_synchronize(hh_ctx ctx);
+
+/* ---------------------------------------------------------------- kernels */
+
+/* Rotne-Prager-Yamakawa tensor for spheres of radius a in a fluid of
+ * viscosity mu (the dilute two-body mobility the paper cites, Sec. 1); self
+ * mobility alpha_1 = 1/(6 pi mu a) I (Eq. (2)). Requires a > 0, mu > 0. */
+hh_status hh_kernel_create_rpy(hh_ctx ctx, double a, double mu, hh_kernel* out);
+
+/* Seeded MLP stand-in for the learned two-body term h/|r| of Eq. (4):
+ * o = W4 tanh(W3 tanh(W2 tanh(W1 v + b1) + b2) + b3) + b4, O = o as 3x3
+ * row-major, K(r) = (O + O^T)/2 / (8 pi |r|), v per `input_mode`.
+ * params: host, HH_MLP_NPARAM doubles (layout above); copied. The self
+ * mobility is 1/(6 pi mu a). */
+hh_status hh_kernel_create_mlp(hh_ctx ctx, const double* params, int input_mode, double a,
+                               double mu, hh_kernel* out);
+void hh_kernel_free(hh_kernel k);
+
+/* ----------------------------------------------------------- the hot path */
+
+/* Cluster tree (Definition 1; bisection of boxes along x, y, z, Fig. 2).
+ * X: device FP64 [n][3]. c_leaf >= 2: a cluster with fewer than c_leaf
+ * particles is a leaf. The root box is the power-of-two cube anchored at the
+ * per-axis minimum of X; particles are ordered by 63-bit Morton key of their
+ * 21-bit quantised coordinates, ties by input index; nodes are numbered in
+ * pre-order. Errors: n < 1, c_leaf < 2, n >= 2^31 or non-finite X ->
+ * HH_ERR_INVALID_ARG; two identical positions -> HH_ERR_DUPLICATE_POINTS.
+ * Syncs. */
+hh_status hh_build_tree(hh_ctx ctx, const double* X, int64_t n, int32_t c_leaf, hh_tree* out);
+
+/* Block partition (Algorithm 1) with the admissibility test Eq. (7) on tight
+ * bounding boxes of the member centres: admissible iff dist^2 > 0 and
+ * max(diam_tau^2, diam_sigma^2) <= eta^2 dist^2. eta > 0. dense_mode != 0
+ * admits nothing (every leaf pair is dense), which reproduces the dense
+ * product. Output lists are sorted by (tau, sigma) node id. Syncs. */
+hh_status hh_partition(hh_ctx ctx, hh_tree tree, double eta, int dense_mode, hh_part* out);
+
+/* Adaptive cross approximation (Algorithm 2, Eqs. (8)-(10)) of every
+ * admissible block, with 3x3 entries: first column j_1 = floor(q/2), row and
+ * column pivots by largest squared Frobenius norm of the residual entry (ties
+ * to the lowest index), c_k normalised by the inverse of its pivot entry,
+ * stop when nu^2 <= eps^2 lambda^2 (exact block norms through 3x3 Gram
+ * matrices) or when min(c, q) terms interpolate the block. A block that
+ * reaches l_max terms without converging is evaluated densely by hh_matvec
+ * (counted in hh_lowrank_info). eps >= 0, 1 <= l_max <= 64. Syncs. */
+hh_status hh_aca_build(hh_ctx ctx, hh_tree tree, hh_part part, hh_kernel kern,
+                       hh_precision prec, double eps, int32_t l_max, hh_lowrank* out);
+
+/* U = alpha_1 F + sum_{P^H} H F + sum_{P^G} C (Q F)  (Eq. (6), first two
+ * terms). F: device [n][3] (FP64 for HH_FP64, FP32 otherwise). U: device
+ * [n][3] (FP32 for HH_FP32, FP64 otherwise), fully overwritten, input order.
+ * lr must come from hh_aca_build with the same tree, partition, kernel and
+ * precision. Does not sync. */
+hh_status hh_matvec(hh_ctx ctx, hh_tree tree, hh_part part, hh_lowrank lr, hh_kernel kern,
+                    hh_precision prec, const void* F, void* U);
+
+/* Gradients of L = sum_i dU_i . U_i for the product hh_matvec computes, with
+ * the tree, the partition and the ACA pivots frozen.
+ *   dF (device, same type as F, nullable): the transposed product M_H^T dU.
+ *   dX (device FP64 [n][3], nullable): d L / d x through the kernel (near
+ *       blocks re-evaluate each pair; admissible blocks use the frozen
+ *       cross approximation as the function of X it is).
+ *   dparams (device FP64 [HH_MLP_NPARAM], nullable, MLP kernel only):
+ *       d L / d theta, accumulated into (not overwritten).
+ * F and dU as in hh_matvec. Precision HH_FP64 or HH_FP32. Does not sync. */
+hh_status hh_matvec_backward(hh_ctx ctx, hh_tree tree, hh_part part, hh_lowrank lr,
+                             hh_kernel kern, hh_precision prec, const void* F, const void* dU,
+                             void* dF, double* dX, double* dparams);
+
+void hh_tree_free(hh_tree t);
+void hh_part_free(hh_part p);
+void hh_lowrank_free(hh_lowrank l);
+
+/* ------------------------------------------------------- export and stats */
+
+/* Sizes of a tree: particles, nodes, leaves. Host outputs (nullable). */
+hh_status hh_tree_info(hh_tree t, int64_t* n, int64_t* n_nodes, int64_t* n_leaves);
+/* Copy a tree to host arrays (each nullable):
+ * perm[n] int64 -- input index at sorted position s; keys[n] uint64 -- Morton
+ * key at sorted position s; nodes[n_nodes][4] int32 -- (begin, end, left,
+ * right), -1 children for leaves; bbox[n_nodes][6] FP64 -- (lo xyz, hi xyz).
+ * Syncs. */
+hh_status hh_tree_export(hh_tree t, int64_t* perm, uint64_t* keys, int32_t* nodes, double* bbox);
+
+/* Sizes of a partition: admissible (nG) and inadmissible (nH) blocks. */
+hh_status hh_part_info(hh_part p, int64_t* nG, int64_t* nH);
+/* Work measures of a partition: near_pairs = sum over P^H of |tau||sigma|
+ * (the dense kernel evaluations of the near field, self pairs included) and
+ * far_entries = sum over P^G of |tau||sigma|. Host outputs (nullable). */
+hh_status hh_part_stats(hh_part p, int64_t* near_pairs, int64_t* far_entries);
+/* Copy the block lists to host arrays [nG][2], [nH][2] of (tau, sigma) node
+ * ids, sorted. Each nullable. Syncs. */
+hh_status hh_part_export(hh_part p, int32_t* G, int32_t* H);
+
+/* Factor summary: number of admissible blocks, sum of ranks, number of
+ * dense fallbacks, total kernel samples taken (sum over blocks of
+ * rank*(c+q)), factor bytes. Host outputs (nullable). */
+hh_status hh_lowrank_info(hh_lowrank l, int64_t* n_blocks, int64_t* rank_sum,
+                          int64_t* n_fallback, int64_t* samples, int64_t* bytes);
+/* Per admissible block (in partition order): rank[nG] int32, fallback flag
+ * [nG] int32, and the pivots piv_i[nG][64], piv_j[nG][64] int32 (local
+ * indices, -1 past the rank). Each nullable. Syncs. */
+hh_status hh_lowrank_export(hh_lowrank l, int32_t* rank, int32_t* fallback, int32_t* piv_i,
+                            int32_t* piv_j);
+/* Copy factor k of admissible block b to host: c_k as [c][3][3] and q_k as
+ * [q][3][3], in FP64 regardless of storage type. Syncs. */
+hh_status hh_lowrank_factor(hh_lowrank l, int64_t b, int32_t k, double* ck, double* qk);
+
+/* ------------------------------------------------------------ profiling */
+
+/* Phases timed with HIP events recorded on the context stream around each
+ * phase's kernel launches, while profiling is on (off by default). */
+#define HH_PHASE_TREE 0      /* hh_build_tree (whole call, incl. its readbacks) */
+#define HH_PHASE_PARTITION 1 /* hh_partition (whole call, incl. its readbacks) */
+#define HH_PHASE_ACA 2       /* the ACA kernel launch(es) of hh_aca_build */
+#define HH_PHASE_NEAR 3      /* the near-field kernel launch of hh_matvec */
+#define HH_PHASE_FAR 4       /* the t_k = Q_k F launch of hh_matvec */
+#define HH_PHASE_COMBINE 5   /* the combine/unpermute launch of hh_matvec */
+#define HH_NPHASE 8
+hh_status hh_ctx_set_profiling(hh_ctx ctx, int on);
+/* Accumulated milliseconds and event pairs per phase since the last reset
+ * (host arrays of HH_NPHASE, nullable). Syncs. reset != 0 clears them after
+ * reading. */
+hh_status hh_ctx_phase_times(hh_ctx ctx, double* ms, int64_t* count, int reset);
+
+/* Build-time constants of the library (for tests): returns 1 if compiled for
+ * gfx950. */
+int hh_device_arch_ok(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HH_H */

@@ -1,0 +1,11 @@
+"""MI355X-native H-matrix mobility product U = M(X) F (arXiv 2505.08174, Sec. 3).
+
+The work runs in the HIP library libhh.so (C ABI in include/hh.h); this package
+only marshals arguments. Importing it does not load the library; the first
+call does, and raises if the library has not been built.
+"""
+from ._lib import HHError, load  # noqa: F401
+from .api import (  # noqa: F401
+    Context, Kernel, Tree, Partition, LowRank, HMatrix, build_tree, partition, aca_build, matvec,
+    hmatvec, pack_mlp, PRECISION,
+)

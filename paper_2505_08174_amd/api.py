@@ -1,0 +1,244 @@
+"""Python face of the C ABI: same call names, torch tensors for device memory
+and the current torch stream for ordering. Every step runs in libhh.so."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+PRECISION = {"fp64": L.HH_FP64, "fp32": L.HH_FP32, "bf16": L.HH_BF16}
+F_DTYPE = {L.HH_FP64: torch.float64, L.HH_FP32: torch.float32, L.HH_BF16: torch.float32}
+U_DTYPE = {L.HH_FP64: torch.float64, L.HH_FP32: torch.float32, L.HH_BF16: torch.float64}
+
+
+def _prec(p):
+    return PRECISION[p] if isinstance(p, str) else int(p)
+
+
+def _ptr(t: torch.Tensor):
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A library context bound to a device and (by default) torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        lib = L.load()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        st = lib.hh_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h))
+        if st != L.HH_OK:
+            raise L.HHError(st, "hh_ctx_create failed")
+        self.h = h
+
+    def check(self, status):
+        L.check(self.h, status)
+
+    def set_stream(self, stream):
+        self.check(L.load().hh_ctx_set_stream(self.h, C.c_void_p(stream.cuda_stream)))
+
+    def synchronize(self):
+        self.check(L.load().hh_synchronize(self.h))
+
+    def set_budget(self, nbytes: int):
+        self.check(L.load().hh_ctx_set_budget(self.h, int(nbytes)))
+
+    def set_profiling(self, on: bool):
+        self.check(L.load().hh_ctx_set_profiling(self.h, int(bool(on))))
+
+    def phase_times(self, reset: bool = False):
+        """{phase: (ms, count)} accumulated while profiling was on."""
+        ms = (C.c_double * L.HH_NPHASE)()
+        cnt = (C.c_int64 * L.HH_NPHASE)()
+        self.check(L.load().hh_ctx_phase_times(self.h, ms, cnt, int(bool(reset))))
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(L.PHASES)}
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                L.load().hh_ctx_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+class _Handle:
+    _free = None
+
+    def __init__(self, ctx, h, keep=()):
+        self.ctx, self.h, self._keep = ctx, h, keep
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                getattr(L.load(), self._free)(self.h)
+                self.h = None
+        except Exception:   # interpreter shutdown: the library is already gone
+            pass
+
+
+class Kernel(_Handle):
+    _free = "hh_kernel_free"
+
+    @staticmethod
+    def rpy(ctx: Context, a: float = 1.0, mu: float = 1.0):
+        h = C.c_void_p()
+        ctx.check(L.load().hh_kernel_create_rpy(ctx.h, a, mu, C.byref(h)))
+        k = Kernel(ctx, h)
+        k.kind, k.a, k.mu = "rpy", a, mu
+        return k
+
+    @staticmethod
+    def mlp(ctx: Context, params, input_mode: str = "direction", a: float = 1.0, mu: float = 1.0):
+        """params: packed FP64 vector (W1,b1,...,W4,b4) or (Ws, bs) lists."""
+        p = pack_mlp(params) if isinstance(params, (tuple, list)) else np.ascontiguousarray(
+            params, dtype=np.float64)
+        assert p.size == L.HH_MLP_NPARAM
+        mode = {"direction": L.HH_MLP_INPUT_DIRECTION,
+                "displacement": L.HH_MLP_INPUT_DISPLACEMENT}[input_mode]
+        h = C.c_void_p()
+        ctx.check(L.load().hh_kernel_create_mlp(ctx.h, p.ctypes.data_as(C.POINTER(C.c_double)),
+                                                mode, a, mu, C.byref(h)))
+        k = Kernel(ctx, h)
+        k.kind, k.a, k.mu, k.params, k.input_mode = "mlp", a, mu, p, input_mode
+        return k
+
+
+def pack_mlp(params):
+    Ws, bs = params
+    parts = []
+    for W, b in zip(Ws, bs):
+        parts.append(np.asarray(W, dtype=np.float64).ravel())
+        parts.append(np.asarray(b, dtype=np.float64).ravel())
+    return np.ascontiguousarray(np.concatenate(parts))
+
+
+class Tree(_Handle):
+    _free = "hh_tree_free"
+
+    def info(self):
+        n, nn, nl = C.c_int64(), C.c_int64(), C.c_int64()
+        self.ctx.check(L.load().hh_tree_info(self.h, C.byref(n), C.byref(nn), C.byref(nl)))
+        return n.value, nn.value, nl.value
+
+    def export(self):
+        n, nn, _ = self.info()
+        perm = np.empty(n, np.int64)
+        keys = np.empty(n, np.uint64)
+        nodes = np.empty((nn, 4), np.int32)
+        bbox = np.empty((nn, 6), np.float64)
+        self.ctx.check(L.load().hh_tree_export(
+            self.h, perm.ctypes.data_as(C.POINTER(C.c_int64)),
+            keys.ctypes.data_as(C.POINTER(C.c_uint64)), nodes.ctypes.data_as(C.POINTER(C.c_int32)),
+            bbox.ctypes.data_as(C.POINTER(C.c_double))))
+        return {"perm": perm, "keys": keys, "nodes": nodes, "bbox": bbox}
+
+
+class Partition(_Handle):
+    _free = "hh_part_free"
+
+    def info(self):
+        g, h = C.c_int64(), C.c_int64()
+        self.ctx.check(L.load().hh_part_info(self.h, C.byref(g), C.byref(h)))
+        return g.value, h.value
+
+    def stats(self):
+        a, b = C.c_int64(), C.c_int64()
+        self.ctx.check(L.load().hh_part_stats(self.h, C.byref(a), C.byref(b)))
+        return {"near_pairs": a.value, "far_entries": b.value}
+
+    def export(self):
+        ng, nh = self.info()
+        G = np.empty((ng, 2), np.int32)
+        H = np.empty((nh, 2), np.int32)
+        self.ctx.check(L.load().hh_part_export(self.h, G.ctypes.data_as(C.POINTER(C.c_int32)),
+                                               H.ctypes.data_as(C.POINTER(C.c_int32))))
+        return G, H
+
+
+class LowRank(_Handle):
+    _free = "hh_lowrank_free"
+
+    def info(self):
+        v = [C.c_int64() for _ in range(5)]
+        self.ctx.check(L.load().hh_lowrank_info(self.h, *[C.byref(x) for x in v]))
+        keys = ("n_blocks", "rank_sum", "n_fallback", "samples", "bytes")
+        return dict(zip(keys, [x.value for x in v]))
+
+    def export(self):
+        nb = self.info()["n_blocks"]
+        rank = np.empty(nb, np.int32)
+        fb = np.empty(nb, np.int32)
+        pi = np.empty((nb, L.LMAX_CAP), np.int32)
+        pj = np.empty((nb, L.LMAX_CAP), np.int32)
+        p32 = C.POINTER(C.c_int32)
+        self.ctx.check(L.load().hh_lowrank_export(self.h, rank.ctypes.data_as(p32),
+                                                  fb.ctypes.data_as(p32), pi.ctypes.data_as(p32),
+                                                  pj.ctypes.data_as(p32)))
+        return {"rank": rank, "fallback": fb, "piv_i": pi, "piv_j": pj}
+
+    def factor(self, b: int, k: int, c: int, q: int):
+        ck = np.empty((c, 3, 3))
+        qk = np.empty((q, 3, 3))
+        pd = C.POINTER(C.c_double)
+        self.ctx.check(L.load().hh_lowrank_factor(self.h, b, k, ck.ctypes.data_as(pd),
+                                                  qk.ctypes.data_as(pd)))
+        return ck, qk
+
+
+def build_tree(ctx: Context, X: torch.Tensor, c_leaf: int) -> Tree:
+    assert X.is_cuda and X.dtype == torch.float64 and X.dim() == 2 and X.shape[1] == 3
+    X = X.contiguous()
+    h = C.c_void_p()
+    ctx.check(L.load().hh_build_tree(ctx.h, _ptr(X), X.shape[0], int(c_leaf), C.byref(h)))
+    return Tree(ctx, h)
+
+
+def partition(ctx: Context, tree: Tree, eta: float = 1.0, dense_mode: bool = False) -> Partition:
+    h = C.c_void_p()
+    ctx.check(L.load().hh_partition(ctx.h, tree.h, float(eta), int(bool(dense_mode)), C.byref(h)))
+    return Partition(ctx, h, keep=(tree,))
+
+
+def aca_build(ctx: Context, tree: Tree, part: Partition, kern: Kernel, prec="fp64",
+              eps: float = 1e-6, l_max: int = 48) -> LowRank:
+    h = C.c_void_p()
+    ctx.check(L.load().hh_aca_build(ctx.h, tree.h, part.h, kern.h, _prec(prec), float(eps),
+                                    int(l_max), C.byref(h)))
+    return LowRank(ctx, h, keep=(tree, part, kern))
+
+
+def matvec(ctx: Context, tree: Tree, part: Partition, lr: LowRank, kern: Kernel, F: torch.Tensor,
+           prec="fp64", U: torch.Tensor | None = None) -> torch.Tensor:
+    p = _prec(prec)
+    assert F.is_cuda and F.dtype == F_DTYPE[p] and F.shape == (tree.info()[0], 3)
+    F = F.contiguous()
+    if U is None:
+        U = torch.empty(F.shape, dtype=U_DTYPE[p], device=F.device)
+    assert U.dtype == U_DTYPE[p] and U.is_contiguous() and U.shape == F.shape
+    ctx.check(L.load().hh_matvec(ctx.h, tree.h, part.h, lr.h, kern.h, p, _ptr(F), _ptr(U)))
+    return U
+
+
+class HMatrix:
+    """Tree + partition + factors for one configuration X (rebuilt when X moves)."""
+
+    def __init__(self, ctx, X, kern, c_leaf=64, eta=1.0, eps=1e-6, prec="fp64", l_max=48,
+                 dense_mode=False):
+        self.ctx, self.kern, self.prec = ctx, kern, _prec(prec)
+        self.tree = build_tree(ctx, X, c_leaf)
+        self.part = partition(ctx, self.tree, eta, dense_mode)
+        self.lr = aca_build(ctx, self.tree, self.part, kern, self.prec, eps, l_max)
+
+    def __matmul__(self, F):
+        return matvec(self.ctx, self.tree, self.part, self.lr, self.kern, F, self.prec)
+
+
+def hmatvec(ctx, X, F, kern, c_leaf=64, eta=1.0, eps=1e-6, prec="fp64", l_max=48):
+    """One full step: tree, partition, ACA and product."""
+    return HMatrix(ctx, X, kern, c_leaf, eta, eps, prec, l_max) @ F

@@ -1,0 +1,248 @@
+// Context, device memory, kernel handles and host readbacks.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+
+#include "api_guard.h"
+#include "internal.h"
+
+void DevBuf::release() {
+  if (p) {
+    (void)hipFreeAsync(p, s);
+    p = nullptr;
+    bytes = 0;
+  }
+}
+
+void DevBuf::alloc(hipStream_t stream, size_t nbytes) {
+  release();
+  s = stream;
+  if (nbytes == 0) nbytes = 256;
+  hipError_t e = hipMallocAsync(&p, nbytes, stream);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    throw hh_error{HH_ERR_OUT_OF_MEMORY,
+                   "device allocation of " + std::to_string(nbytes) + " bytes failed"};
+  }
+  bytes = nbytes;
+}
+
+static hipEvent_t take_event(hh_ctx ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIP_OK(hipEventCreate(&e));
+  return e;
+}
+
+PhaseTimer::PhaseTimer(hh_ctx c, int ph) : ctx(c), phase(ph) {
+  if (!ctx->profiling) return;
+  a = take_event(ctx);
+  (void)hipEventRecord(a, ctx->stream);
+}
+
+PhaseTimer::~PhaseTimer() {
+  if (!a) return;
+  hipEvent_t b = nullptr;
+  try {
+    b = take_event(ctx);
+  } catch (...) {
+    ctx->event_pool.push_back(a);
+    return;
+  }
+  (void)hipEventRecord(b, ctx->stream);
+  ctx->pending.push_back(PhaseRec{phase, a, b});
+}
+
+static void drain_phases(hh_ctx ctx) {
+  if (ctx->pending.empty()) return;
+  ctx_sync(ctx);
+  for (auto& r : ctx->pending) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      ctx->phase_ms[r.phase] += ms;
+      ctx->phase_cnt[r.phase] += 1;
+    }
+    ctx->event_pool.push_back(r.a);
+    ctx->event_pool.push_back(r.b);
+  }
+  ctx->pending.clear();
+}
+
+size_t elem_size(int prec) { return prec == HH_FP64 ? 8 : 4; }
+
+void ctx_sync(hh_ctx ctx) { HIP_OK(hipStreamSynchronize(ctx->stream)); }
+
+void read_bytes(hh_ctx ctx, void* host, const void* dev, size_t bytes) {
+  if (bytes == 0) return;
+  HIP_OK(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
+  ctx_sync(ctx);
+}
+
+int64_t read_i64(hh_ctx ctx, const void* dev_ptr) {
+  HIP_OK(hipMemcpyAsync(ctx->pinned, dev_ptr, 8, hipMemcpyDeviceToHost, ctx->stream));
+  ctx_sync(ctx);
+  return ctx->pinned[0];
+}
+
+extern "C" {
+
+hh_status hh_ctx_create(int device, void* stream, hh_ctx* out) {
+  if (!out) return HH_ERR_INVALID_ARG;
+  *out = nullptr;
+  hh_ctx ctx = new (std::nothrow) hh_ctx_s();
+  if (!ctx) return HH_ERR_OUT_OF_MEMORY;
+  try {
+    int n = 0;
+    HIP_OK(hipGetDeviceCount(&n));
+    HH_REQUIRE(device >= 0 && device < n, HH_ERR_INVALID_ARG, "no such HIP device");
+    HIP_OK(hipSetDevice(device));
+    ctx->device = device;
+    ctx->stream = (hipStream_t)stream;
+    // keep freed blocks in the stream-ordered pool for reuse across steps
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+      uint64_t thr = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    size_t fr = 0, tot = 0;
+    HIP_OK(hipMemGetInfo(&fr, &tot));
+    ctx->budget_bytes = (size_t)(0.4 * (double)fr);
+    ctx->scratch_flag.alloc(ctx->stream, 64 * sizeof(int64_t));
+    HIP_OK(hipHostMalloc((void**)&ctx->pinned, 64 * sizeof(int64_t), hipHostMallocDefault));
+  } catch (const hh_error& e) {
+    delete ctx;
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    delete ctx;
+    return HH_ERR_OUT_OF_MEMORY;
+  }
+  *out = ctx;
+  return HH_OK;
+}
+
+void hh_ctx_destroy(hh_ctx ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  ctx->scratch_flag.release();
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& r : ctx->pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  delete ctx;
+}
+
+const char* hh_last_error(hh_ctx ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+
+hh_status hh_ctx_set_stream(hh_ctx ctx, void* stream) {
+  if (!ctx) return HH_ERR_INVALID_ARG;
+  ctx->stream = (hipStream_t)stream;
+  return HH_OK;
+}
+
+hh_status hh_ctx_set_budget(hh_ctx ctx, size_t bytes) {
+  HH_API_BEGIN(ctx)
+  HH_REQUIRE(bytes >= 4096, HH_ERR_INVALID_ARG, "budget must be at least 4096 bytes");
+  ctx->budget_bytes = bytes;
+  HH_API_END(ctx)
+}
+
+hh_status hh_ctx_set_profiling(hh_ctx ctx, int on) {
+  HH_API_BEGIN(ctx)
+  ctx->profiling = on != 0;
+  HH_API_END(ctx)
+}
+
+hh_status hh_ctx_phase_times(hh_ctx ctx, double* ms, int64_t* count, int reset) {
+  HH_API_BEGIN(ctx)
+  drain_phases(ctx);
+  for (int i = 0; i < HH_NPHASE; ++i) {
+    if (ms) ms[i] = ctx->phase_ms[i];
+    if (count) count[i] = ctx->phase_cnt[i];
+    if (reset) {
+      ctx->phase_ms[i] = 0;
+      ctx->phase_cnt[i] = 0;
+    }
+  }
+  HH_API_END(ctx)
+}
+
+hh_status hh_synchronize(hh_ctx ctx) {
+  HH_API_BEGIN(ctx)
+  ctx_sync(ctx);
+  HH_API_END(ctx)
+}
+
+hh_status hh_kernel_create_rpy(hh_ctx ctx, double a, double mu, hh_kernel* out) {
+  if (out) *out = nullptr;
+  HH_API_BEGIN(ctx)
+  HH_REQUIRE(out, HH_ERR_INVALID_ARG, "out is NULL");
+  HH_REQUIRE(a > 0 && mu > 0 && isfinite(a) && isfinite(mu), HH_ERR_INVALID_ARG,
+             "RPY kernel needs a > 0 and mu > 0");
+  hh_kernel k = new hh_kernel_s();
+  k->ctx = ctx;
+  k->kind = KIND_RPY;
+  k->a = a;
+  k->mu = mu;
+  k->alpha1 = 1.0 / (6.0 * M_PI * mu * a);
+  *out = k;
+  HH_API_END(ctx)
+}
+
+hh_status hh_kernel_create_mlp(hh_ctx ctx, const double* params, int input_mode, double a,
+                               double mu, hh_kernel* out) {
+  if (out) *out = nullptr;
+  HH_API_BEGIN(ctx)
+  HH_REQUIRE(out && params, HH_ERR_INVALID_ARG, "NULL argument");
+  HH_REQUIRE(input_mode == HH_MLP_INPUT_DIRECTION || input_mode == HH_MLP_INPUT_DISPLACEMENT,
+             HH_ERR_INVALID_ARG, "unknown MLP input mode");
+  HH_REQUIRE(a > 0 && mu > 0, HH_ERR_INVALID_ARG, "MLP kernel needs a > 0 and mu > 0");
+  for (int i = 0; i < MLP_NP; ++i)
+    HH_REQUIRE(isfinite(params[i]), HH_ERR_INVALID_ARG, "non-finite MLP parameter");
+  hh_kernel_s* k = new hh_kernel_s();
+  try {
+    k->ctx = ctx;
+    k->kind = KIND_MLP;
+    k->input_mode = input_mode;
+    k->a = a;
+    k->mu = mu;
+    k->alpha1 = 1.0 / (6.0 * M_PI * mu * a);
+    k->host_params.assign(params, params + MLP_NP);
+    std::vector<float> p32(params, params + MLP_NP);
+    k->p64.alloc(ctx->stream, MLP_NP * sizeof(double));
+    k->p32.alloc(ctx->stream, MLP_NP * sizeof(float));
+    HIP_OK(hipMemcpyAsync(k->p64.p, params, MLP_NP * sizeof(double), hipMemcpyHostToDevice,
+                          ctx->stream));
+    HIP_OK(hipMemcpyAsync(k->p32.p, p32.data(), MLP_NP * sizeof(float), hipMemcpyHostToDevice,
+                          ctx->stream));
+    ctx_sync(ctx);
+  } catch (...) {
+    delete k;
+    throw;
+  }
+  *out = k;
+  HH_API_END(ctx)
+}
+
+void hh_kernel_free(hh_kernel k) {
+  if (!k) return;
+  delete k;
+}
+
+int hh_device_arch_ok(void) {
+  hipDeviceProp_t p;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipGetDeviceProperties(&p, dev) != hipSuccess) return 0;
+  return strncmp(p.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,187 @@
+// Internal declarations of the MI355X H-matrix library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/hh.h"
+
+#define HH_WAVE 64
+
+// ------------------------------------------------------------------ errors
+
+struct hh_error {
+  hh_status st;
+  std::string msg;
+};
+
+#define HIP_OK(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      throw hh_error{HH_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define HH_REQUIRE(cond, status, text)                 \
+  do {                                                 \
+    if (!(cond)) throw hh_error{status, std::string(text)}; \
+  } while (0)
+
+// ------------------------------------------------------------- device memory
+
+// A stream-ordered device buffer (hipMallocAsync / hipFreeAsync on the
+// context stream). Freed on the stream in the destructor.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipStream_t s = nullptr;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release();
+  void alloc(hipStream_t stream, size_t nbytes);
+  template <class T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+struct PhaseRec {
+  int phase;
+  hipEvent_t a, b;
+};
+
+struct hh_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+  DevBuf scratch_flag;   // small device scratch for readbacks (64 x int64)
+  int64_t* pinned = nullptr;  // host pinned mirror for readbacks (64 x int64)
+  bool profiling = false;
+  std::vector<PhaseRec> pending;
+  std::vector<hipEvent_t> event_pool;
+  size_t budget_bytes = 0;     // device memory the ACA may use for factors
+  double phase_ms[HH_NPHASE] = {0};
+  int64_t phase_cnt[HH_NPHASE] = {0};
+};
+
+// Records HIP events around a phase when profiling is on (RAII).
+struct PhaseTimer {
+  hh_ctx ctx;
+  int phase;
+  hipEvent_t a = nullptr;
+  PhaseTimer(hh_ctx c, int ph);
+  ~PhaseTimer();
+};
+
+// --------------------------------------------------------------- the kernel
+
+enum { KIND_RPY = 0, KIND_MLP = 1 };
+
+struct hh_kernel_s {
+  hh_ctx ctx = nullptr;
+  int kind = KIND_RPY;
+  int input_mode = HH_MLP_INPUT_DIRECTION;
+  double a = 1.0, mu = 1.0;
+  double alpha1 = 0.0;
+  std::vector<double> host_params;  // MLP, packed (HH_MLP_NPARAM)
+  DevBuf p64;                       // MLP params FP64, packed
+  DevBuf p32;                       // MLP params FP32, packed
+  DevBuf pbf;                       // MLP params for the BF16 MFMA path
+};
+
+// Offsets of the packed MLP parameter vector.
+#define MLP_H 64
+#define OFF_W1 0
+#define OFF_B1 (OFF_W1 + MLP_H * 3)
+#define OFF_W2 (OFF_B1 + MLP_H)
+#define OFF_B2 (OFF_W2 + MLP_H * MLP_H)
+#define OFF_W3 (OFF_B2 + MLP_H)
+#define OFF_B3 (OFF_W3 + MLP_H * MLP_H)
+#define OFF_W4 (OFF_B3 + MLP_H)
+#define OFF_B4 (OFF_W4 + 9 * MLP_H)
+#define MLP_NP (OFF_B4 + 9)
+static_assert(MLP_NP == HH_MLP_NPARAM, "packed MLP layout");
+
+// ----------------------------------------------------------------- the tree
+
+struct hh_tree_s {
+  hh_ctx ctx = nullptr;
+  int64_t n = 0;
+  int32_t c_leaf = 0;
+  int64_t n_nodes = 0, n_leaves = 0;
+  DevBuf perm;      // int32 [n]   input index at sorted position
+  DevBuf keys;      // uint64 [n]  sorted Morton keys
+  DevBuf xs;        // double [n][3] sorted positions
+  DevBuf nodes;     // int4 [n_nodes] (begin, end, left, right)
+  DevBuf parent;    // int32 [n_nodes]
+  DevBuf bbox;      // double [n_nodes][6]
+  DevBuf leaf_id;   // int32 [n_nodes] rank among leaves, -1 for internal
+  DevBuf leaves;    // int32 [n_leaves] node id of each leaf, in order
+  DevBuf leaf_of;   // int32 [n] leaf node of sorted position s
+};
+
+// ------------------------------------------------------------ the partition
+
+struct hh_part_s {
+  hh_ctx ctx = nullptr;
+  hh_tree tree = nullptr;
+  int64_t nG = 0, nH = 0;
+  DevBuf G;        // int2 [nG] (tau, sigma) sorted
+  DevBuf H;        // int2 [nH] (tau, sigma) sorted
+  DevBuf near_ptr; // int32 [n_leaves+1] CSR of H by target leaf rank
+  DevBuf far_ptr;  // int32 [n_nodes+1]  CSR of G by target node
+  int64_t near_pairs = 0;   // sum over H of |tau||sigma|
+  int64_t far_entries = 0;  // sum over G of |tau||sigma|
+};
+
+// ----------------------------------------------------- low-rank factors
+
+#define LMAX_CAP 64
+
+struct hh_lowrank_s {
+  hh_ctx ctx = nullptr;
+  hh_part part = nullptr;
+  int prec = HH_FP64;
+  int64_t nG = 0;
+  int32_t l_max = 0;
+  double eps = 0.0;
+  DevBuf rank;      // int32 [nG]
+  DevBuf flag;      // int32 [nG] 1 = dense fallback
+  DevBuf piv;       // int32 [nG][2][LMAX_CAP] (i_k then j_k), local indices
+  DevBuf fptr;      // int64 [nG][LMAX_CAP] element offset of factor k in pool
+  DevBuf pool;      // factor storage (double or float), (c + q) * 9 per factor
+  int64_t pool_elems = 0;
+  int64_t rank_sum = 0, n_fallback = 0, samples = 0, used_elems = 0;
+  DevBuf toff;      // int64 [nG] offset of the block's t vectors (rank*3)
+  DevBuf tbuf;      // t_k = Q_k F  storage (double), [rank_sum][3]
+  // streamed mode: factors live only inside a batch of blocks
+  bool streamed = false;
+  bool stats_dirty = true;
+  hh_kernel kern = nullptr;
+  int64_t est_elems = 0;
+  std::vector<int64_t> bounds;   // batch block boundaries
+  int64_t ub_elems = 0;          // largest batch sum of c
+  DevBuf uoff;                   // int64 [nG+1] prefix sums of c
+  DevBuf ublk;                   // double [ub_elems][3]
+};
+
+// ------------------------------------------------------------- helpers
+
+size_t elem_size(int prec);
+void ctx_sync(hh_ctx ctx);
+int64_t read_i64(hh_ctx ctx, const void* dev_ptr);
+void read_bytes(hh_ctx ctx, void* host, const void* dev, size_t bytes);
+
+// Scan / sort primitives (sort.hip).
+// Exclusive prefix sum of n int64 values (in place allowed: in == out).
+void scan_exclusive_i64(hh_ctx ctx, const int64_t* in, int64_t* out, int64_t n);
+// Stable LSD radix sort of (key, value) pairs by the low `bits` bits of key.
+void radix_sort_u64(hh_ctx ctx, uint64_t* keys, uint32_t* vals, int64_t n, int bits);
+
+// Near-field, ACA, far-field and combine launches (near.hip, aca.hip, apply.hip).
+void launch_near(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, int prec, const void* F,
+                 void* Unear);
+void launch_aca(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr, double eps,
+                int32_t l_max, int64_t* pool_top_dev);

@@ -1,0 +1,165 @@
+"""GPU parity of the H-matrix product against the FP64 oracle.
+
+* dense mode (no admissible block) reproduces the exact dense sum: FP64
+  within 1e-10 relative (RPY and MLP);
+* FP64 H-matvec with RPY at zeta = 1e-6 is within 10 zeta of the dense sum
+  and within zeta of the oracle's own H-matrix product (a borderline stopping
+  test may add or drop one term of size ~zeta lambda), with the ACA pivots and
+  ranks equal to the oracle's on (almost) every block;
+* FP32 with the MLP kernel within 1e-3 of the dense sum;
+* where the pivots agree with the oracle's, the factors c_k, q_k agree with
+  the oracle's to 1e-9 (Frobenius, per factor).
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2505_08174_amd as hh
+import workloads as wl
+from oracle import dense as OD
+from oracle import hmatvec as OH
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+@pytest.mark.parametrize("kind", ["rpy", "mlp"])
+def test_dense_mode_fp64(kind):
+    from gpu_common import ctx, dev, kernels, say
+    say("dense mode fp64", kind)
+    n = 2000 if kind == "rpy" else 700
+    X = wl.rsa_cube(n, 0.1, seed=0)
+    F = wl.normal_forces(n, seed=0)
+    ko, kg = kernels(kind)
+    Ud = OD.dense_u(X, F, ko)
+    hm = hh.HMatrix(ctx(), dev(X), kg, c_leaf=64, prec="fp64", dense_mode=True)
+    U = (hm @ dev(F)).cpu().numpy()
+    assert _rel(U, Ud) < 1e-10
+
+
+def test_hmatvec_fp64_rpy_plain_small():
+    from gpu_common import ctx, dev, kernels, say
+    say("plain small fp64 rpy")
+    X, F, cfg = wl.workload("plain_small")
+    ko, kg = kernels("rpy")
+    Ud = OD.dense_u(X, F, ko)
+    hm = hh.HMatrix(ctx(), dev(X), kg, c_leaf=64, eta=1.0, eps=1e-6, prec="fp64")
+    U = (hm @ dev(F)).cpu().numpy()
+    e = _rel(U, Ud)
+    say("eps_r", e)
+    assert e <= 1e-5
+    # against the oracle's literal H-matrix product: pivots and ranks first
+    ref = OH.build(X, ko, 64, 1.0, 1e-6, 48)
+    ex = hm.lr.export()
+    ranks = np.array([0 if b is None else b.rank for b in ref.blocks])
+    same = same_piv = 0
+    for b, blk in enumerate(ref.blocks):
+        r = ex["rank"][b]
+        if blk is None:
+            continue
+        m = min(r, blk.rank)
+        if np.array_equal(ex["piv_i"][b, :m], blk.piv_i[:m]) and \
+                np.array_equal(ex["piv_j"][b, :m], blk.piv_j[:m]):
+            same_piv += 1
+            same += int(r == blk.rank)
+    say("blocks", len(ref.blocks), "same pivots", same_piv, "same pivots and rank", same,
+        "rank sums", int(ex["rank"].sum()), int(ranks.sum()))
+    assert same_piv >= 0.99 * len(ref.blocks)
+    assert same >= 0.95 * len(ref.blocks)
+    assert ex["fallback"].sum() == ref.n_fallback
+    # a borderline stopping test may end a block one term earlier or later
+    # (a term of size ~ zeta * lambda), so the two H products agree to ~zeta
+    Uo = OH.apply(ref, X, F, ko)
+    d = _rel(U, Uo)
+    say("gpu vs oracle H", d)
+    assert d < 1e-6
+
+
+def test_factors_match_oracle_fp64():
+    from gpu_common import ctx, dev, kernels, say
+    say("factors fp64")
+    X = wl.rsa_cube(1500, 0.15, seed=5)
+    ko, kg = kernels("rpy")
+    hm = hh.HMatrix(ctx(), dev(X), kg, c_leaf=32, eta=1.0, eps=1e-5, prec="fp64")
+    ref = OH.build(X, ko, 32, 1.0, 1e-5, 48)
+    ex = hm.lr.export()
+    t = ref.tree
+    checked = 0
+    for b in range(0, len(ref.blocks), max(1, len(ref.blocks) // 25)):
+        blk = ref.blocks[b]
+        r = ex["rank"][b]
+        if blk is None or r != blk.rank or not np.array_equal(ex["piv_i"][b, :r], blk.piv_i):
+            continue
+        tau, sig = ref.G[b]
+        c = t.nodes[tau, 1] - t.nodes[tau, 0]
+        q = t.nodes[sig, 1] - t.nodes[sig, 0]
+        for k in range(r):
+            ck, qk = hm.lr.factor(b, k, c, q)
+            # term k has size nu_k while the rounding noise of the residual it
+            # is cut from is ~u * lambda: relative accuracy ~u * lambda / nu_k
+            tol = max(1e-10, 1e-11 * np.sqrt(blk.lam2[k] / blk.nu2[k]))
+            assert _rel(ck, blk.C[k]) < tol, (b, k, _rel(ck, blk.C[k]), tol)
+            assert _rel(qk, blk.Q[k]) < tol, (b, k, _rel(qk, blk.Q[k]), tol)
+        checked += 1
+    assert checked >= 5
+
+
+@pytest.mark.parametrize("inp", ["direction", "displacement"])
+def test_hmatvec_fp32_mlp(inp):
+    from gpu_common import ctx, dev, kernels, say
+    say("fp32 mlp", inp)
+    n = 4000
+    X = wl.rsa_cube(n, 0.2, seed=0)
+    F = wl.normal_forces(n, seed=0)
+    ko, kg = kernels("mlp", inp)
+    rows = wl.sample_rows(n, 300)
+    Ud = OD.dense_u(X, F, ko, rows)
+    hm = hh.HMatrix(ctx(), dev(X), kg, c_leaf=64, eta=1.0, eps=1e-4, prec="fp32")
+    U = (hm @ dev(F, torch.float32)).cpu().numpy().astype(np.float64)
+    e = _rel(U[rows], Ud)
+    say("eps_r", e, hm.lr.info())
+    assert e <= 1e-3
+
+
+def test_hmatvec_edge_sizes():
+    from gpu_common import ctx, dev, kernels, say
+    ko, kg = kernels("rpy")
+    for n in (1, 2, 5, 64, 65, 300):
+        say("edge", n)
+        X = wl.rsa_cube(n, 0.05, seed=n) if n > 1 else np.zeros((1, 3))
+        F = wl.normal_forces(n, seed=n)
+        hm = hh.HMatrix(ctx(), dev(X), kg, c_leaf=8, eps=1e-8, prec="fp64")
+        U = (hm @ dev(F)).cpu().numpy()
+        assert _rel(U, OD.dense_u(X, F, ko)) < 1e-6
+
+
+@pytest.mark.parametrize("kind,prec,n,eps,tol", [("rpy", "fp64", 2000, 1e-6, 1e-12),
+                                                 ("mlp", "fp32", 4000, 1e-4, 2e-5)])
+def test_streamed_equals_stored(kind, prec, n, eps, tol):
+    """Batches of blocks with the apply fused into the ACA (factors discarded)
+    give the product of the stored factors, to rounding of the summation order."""
+    from gpu_common import ctx, dev, kernels, say
+    say("streamed vs stored", kind, prec, n)
+    X = wl.rsa_cube(n, 0.15, seed=1)
+    F = wl.normal_forces(n, seed=1)
+    ko, kg = kernels(kind)
+    fdt = torch.float64 if prec == "fp64" else torch.float32
+    hm = hh.HMatrix(ctx(), dev(X), kg, c_leaf=64, eta=1.0, eps=eps, prec=prec)
+    U1 = (hm @ dev(F, fdt)).double().cpu().numpy()
+    info1 = hm.lr.info()
+    ctx().set_budget(2 << 20)           # 2 MiB: forces many small batches
+    try:
+        hs = hh.HMatrix(ctx(), dev(X), kg, c_leaf=64, eta=1.0, eps=eps, prec=prec)
+        U2 = (hs @ dev(F, fdt)).double().cpu().numpy()
+        info2 = hs.lr.info()
+    finally:
+        ctx().set_budget(64 << 30)
+    say("stored", info1, "streamed", info2, "diff", _rel(U2, U1))
+    assert info2["n_blocks"] == info1["n_blocks"]
+    assert abs(info2["rank_sum"] - info1["rank_sum"]) <= 0.002 * info1["rank_sum"]
+    assert _rel(U2, U1) < tol
+    with pytest.raises(hh.HHError, match="streamed"):
+        hs.lr.factor(0, 0, 1, 1)
