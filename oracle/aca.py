@@ -12,8 +12,12 @@ lambda^2 being updated incrementally (Algorithm 2, line 10).
 
 Readings where the paper is silent or inconsistent (listed in the design notes):
   * entry magnitude for pivoting: the squared Frobenius norm of the 3x3 entry
-    (the text around Eq. (9) calls |.| a determinant while Algorithm 2 uses the
-    Frobenius norm; a determinant is not a magnitude);
+    as Algorithm 2 writes it (pivot="frobenius", the default); the text around
+    Eq. (9) instead calls |.| the determinant, which is available as
+    pivot="determinant" (|det| of the entry). The determinant rule never picks
+    a nearly singular 3x3 pivot, which keeps c_k = a P^-1 bounded; the
+    single-precision forms use it. The stopping guards use Frobenius norms
+    under both rules;
   * the initial column is j_1 = floor(q/2) (the paper draws it at random);
   * argmax ties go to the lowest local index;
   * the stopping test is nu^2 <= zeta^2 lambda^2, taken after the term is
@@ -51,17 +55,25 @@ class ACAResult:
         return len(self.piv_i)
 
 
-def aca_block(kern, Xt, Xs, eps: float, l_max: int, piv_j1: int | None = None) -> ACAResult:
+def aca_block(kern, Xt, Xs, eps: float, l_max: int, piv_j1: int | None = None,
+              pivot: str = "frobenius") -> ACAResult:
     """Algorithm 2 on the block G(i, j) = K(Xt[i] - Xs[j])."""
     Xt = np.asarray(Xt, dtype=np.float64)
     Xs = np.asarray(Xs, dtype=np.float64)
     return aca_entries(lambda j: kern(Xt - Xs[j]), lambda i: kern(Xt[i] - Xs),
-                       Xt.shape[0], Xs.shape[0], eps, l_max, piv_j1)
+                       Xt.shape[0], Xs.shape[0], eps, l_max, piv_j1, pivot)
+
+
+def _magnitude(E, pivot):
+    if pivot == "frobenius":
+        return np.sum(E * E, axis=(1, 2))
+    return np.abs(np.linalg.det(E))
 
 
 def aca_entries(col, row, c: int, q: int, eps: float, l_max: int,
-                piv_j1: int | None = None) -> ACAResult:
+                piv_j1: int | None = None, pivot: str = "frobenius") -> ACAResult:
     """Algorithm 2 on a c x q block given by col(j) -> [c,3,3], row(i) -> [q,3,3]."""
+    assert pivot in ("frobenius", "determinant")
     Cs, Qs, I, J, nus, lams = [], [], [], [], [], []
     used_i = np.zeros(c, dtype=bool)
     used_j = np.zeros(q, dtype=bool)
@@ -77,11 +89,10 @@ def aca_entries(col, row, c: int, q: int, eps: float, l_max: int,
             a = a - Cs[m] @ Qs[m][j]
         # line 5: row pivot
         nrm = np.sum(a * a, axis=(1, 2))
-        nrm_masked = np.where(used_i, -1.0, nrm)
-        ik = int(np.argmax(nrm_masked))
-        if nrm_masked[ik] <= TINY * lam2:
+        if np.max(np.where(used_i, -1.0, nrm)) <= TINY * lam2:
             converged = True
             break
+        ik = int(np.argmax(np.where(used_i, -1.0, _magnitude(a, pivot))))
         P = a[ik]
         fro = np.sqrt(np.sum(P * P))
         if abs(np.linalg.det(P)) <= SING * fro ** 3:
@@ -95,7 +106,7 @@ def aca_entries(col, row, c: int, q: int, eps: float, l_max: int,
         qk = b
         used_i[ik] = True
         # line 8: next column pivot
-        nq = np.where(used_j, -1.0, np.sum(qk * qk, axis=(1, 2)))
+        nq = np.where(used_j, -1.0, _magnitude(qk, pivot))
         jn = int(np.argmax(nq))
         # lines 9-10: nu^2 and lambda^2 via 3x3 Gram matrices
         Akk = np.einsum("iab,iac->bc", ck, ck)

@@ -27,7 +27,8 @@ class HMatrix:
         self.n_fallback = n_fallback
 
 
-def build(X, kern, c_leaf, eta=1.0, eps=1e-6, l_max=48, dense_mode=False, tree=None, part=None):
+def build(X, kern, c_leaf, eta=1.0, eps=1e-6, l_max=48, dense_mode=False, tree=None, part=None,
+          pivot="frobenius"):
     X = np.asarray(X, dtype=np.float64)
     if tree is None:
         tree = build_tree(X, c_leaf)
@@ -41,7 +42,7 @@ def build(X, kern, c_leaf, eta=1.0, eps=1e-6, l_max=48, dense_mode=False, tree=N
     for t, s in G:
         bt, et = tree.nodes[t, 0], tree.nodes[t, 1]
         bs, es = tree.nodes[s, 0], tree.nodes[s, 1]
-        res = aca_block(kern, Xs[bt:et], Xs[bs:es], eps, l_max)
+        res = aca_block(kern, Xs[bt:et], Xs[bs:es], eps, l_max, pivot=pivot)
         if not res.converged:
             res = None
             nfb += 1

@@ -11,6 +11,10 @@
 //   nu^2 = tr(A_kk B_kk), lambda^2 += nu^2 + 2 sum_{m<k} tr(A_mk B_km)  (lines 9-10)
 //   with A_mk = sum_i c_m(i)^T c_k(i), B_km = sum_j q_k(j) q_m(j)^T
 //   stop when nu^2 <= eps^2 lambda^2 (line 12) or min(c, q) terms.
+// Pivot magnitude: squared Frobenius norm in the FP64 form (Algorithm 2);
+// |det| of the 3x3 entry in the FP32 and BF16 forms (the magnitude the text
+// around Eq. (9) names), which avoids nearly singular pivots whose inverse
+// would amplify single-precision rounding in c_k = a P^-1.
 // Guards: a residual column with ||a||^2 <= 1e-30 lambda^2 ends as converged
 // without a new term; |det P| <= 1e-14 ||P||_F^3 ends with a dense fallback;
 // l_max terms without convergence end with a dense fallback.
@@ -20,6 +24,7 @@
 // type T; norms, pivots and Gram sums in NT.
 #include "devmath.h"
 #include "internal.h"
+#include "mlp_mfma.h"
 
 namespace {
 
@@ -50,7 +55,32 @@ struct AcaArgs {
   const T* Fs;       // sorted forces
   double* ublk;      // per-block output rows [c][3], at uoff[b] - uoff[b0]
   const int64_t* uoff;
+  const uint4* frags;   // BF16 MFMA weight fragments (MF kernels)
+  int det_pivot;        // pivot magnitude |det| (else squared Frobenius norm)
 };
+
+template <class NT, class T>
+__device__ __forceinline__ NT det3(const T* K) {
+  return fabs((NT)K[0] * ((NT)K[4] * (NT)K[8] - (NT)K[5] * (NT)K[7]) -
+              (NT)K[1] * ((NT)K[3] * (NT)K[8] - (NT)K[5] * (NT)K[6]) +
+              (NT)K[2] * ((NT)K[3] * (NT)K[7] - (NT)K[4] * (NT)K[6]));
+}
+
+// K(x_i - y_j) from the MFMA MLP tile: symmetrised 3x3 entry of a pair.
+__device__ __forceinline__ void mfma_entry(const bf16x8* fr, int mode, double dx, double dy,
+                                           double dz, float K[9]) {
+  float rx = (float)dx, ry = (float)dy, rz = (float)dz;
+  const float rs = hh_rsqrt(rx * rx + ry * ry + rz * rz);
+  float o[9];
+  if (mode == HH_MLP_INPUT_DIRECTION)
+    mlp_tile_bf16<true>(fr, rx * rs, ry * rs, rz * rs, o);
+  else
+    mlp_tile_bf16<true>(fr, rx, ry, rz, o);
+  const float s = rs * (float)(1.0 / (16.0 * HH_PI));
+  K[0] = 2.0f * o[0] * s; K[1] = (o[1] + o[3]) * s; K[2] = (o[2] + o[6]) * s;
+  K[3] = K[1];            K[4] = 2.0f * o[4] * s;   K[5] = (o[5] + o[7]) * s;
+  K[6] = K[2];            K[7] = K[5];              K[8] = 2.0f * o[8] * s;
+}
 
 // block-wide argmax (ties to the lowest index), result broadcast to all threads
 template <class NT>
@@ -66,9 +96,11 @@ __device__ __forceinline__ void block_argmax(NT& v, int& i, NT* sv, int* si) {
     if (sv[k] > v || (sv[k] == v && si[k] < i)) { v = sv[k]; i = si[k]; }
 }
 
-template <class T, class NT, int KIND>
+template <class T, class NT, int KIND, bool MF>
 __global__ __launch_bounds__(ACA_T) void k_aca(AcaArgs<T> a) {
-  __shared__ T wl[KIND == KIND_MLP ? MLP_NP : 1];
+  // MF: kernel samples from the BF16 MFMA MLP (weights as LDS fragments)
+  __shared__ T wl[(KIND == KIND_MLP && !MF) ? MLP_NP : 1];
+  __shared__ bf16x8 fr[MF ? FR_TOTAL : 1];
   __shared__ T s_qj[LMAX_CAP * 9];   // q_m(j_k), m < k
   __shared__ T s_ci[LMAX_CAP * 9];   // c_m(i_k), m < k
   __shared__ T s_pinv[9];
@@ -80,7 +112,9 @@ __global__ __launch_bounds__(ACA_T) void k_aca(AcaArgs<T> a) {
   __shared__ NT s_lam2;
   __shared__ double s_t[NW][3];
   __shared__ int s_b, s_stop, s_fb;
-  if (KIND == KIND_MLP) {
+  if (MF) {
+    stage_frags(fr, a.frags, ACA_T);
+  } else if (KIND == KIND_MLP) {
     const T* w = (const T*)a.kp.w;
     for (int i = threadIdx.x; i < MLP_NP; i += ACA_T) wl[i] = w[i];
   }
@@ -128,14 +162,33 @@ __global__ __launch_bounds__(ACA_T) void k_aca(AcaArgs<T> a) {
       T* Ck = a.pool + s_off[k];
       T* Qk = Ck + 9 * (int64_t)c;
       // line 4-5: residual column j and its largest unused entry
-      NT best = -1;
+      NT best = -1, bestf = -1;   // selection magnitude, largest squared norm
       int bi = 0x7fffffff;
       NT graw = 0;   // largest raw entry of the column (precision floor)
       const double yj0 = xsr[3 * j], yj1 = xsr[3 * j + 1], yj2 = xsr[3 * j + 2];
+      if (MF) {
+        // raw column samples in 32-row MFMA tiles, parked in the c_k slot
+        for (int t0 = 32 * wv; t0 < c; t0 += 32 * NW) {
+          const int i = t0 + (lane & 31);
+          const int ii = i < c ? i : t0;
+          float K[9];
+          mfma_entry(fr, a.kp.input_mode, xt[3 * ii] - yj0, xt[3 * ii + 1] - yj1,
+                     xt[3 * ii + 2] - yj2, K);
+          if (i < c && lane < 32)
+#pragma unroll
+            for (int e = 0; e < 9; ++e) Ck[9 * (int64_t)i + e] = (T)K[e];
+        }
+        __syncthreads();
+      }
       for (int i = tid; i < c; i += ACA_T) {
         T K[9];
-        kernel_entry<T>(a.kp, wl, (T)(xt[3 * i] - yj0), (T)(xt[3 * i + 1] - yj1),
-                        (T)(xt[3 * i + 2] - yj2), K);
+        if (MF) {
+#pragma unroll
+          for (int e = 0; e < 9; ++e) K[e] = Ck[9 * (int64_t)i + e];
+        } else {
+          kernel_entry<T>(a.kp, wl, (T)(xt[3 * i] - yj0), (T)(xt[3 * i + 1] - yj1),
+                          (T)(xt[3 * i + 2] - yj2), K);
+        }
         if (sizeof(T) == 4) {
           NT g2 = 0;
 #pragma unroll
@@ -160,22 +213,30 @@ __global__ __launch_bounds__(ACA_T) void k_aca(AcaArgs<T> a) {
           Ck[9 * (int64_t)i + e] = K[e];
           nrm += (NT)K[e] * (NT)K[e];
         }
+        NT sel = a.det_pivot ? det3<NT>(K) : nrm;
         bool used = false;
         for (int m = 0; m < k; ++m) used |= (s_pi[m] == i);
-        if (used) nrm = -1;
-        if (nrm > best || (nrm == best && i < bi)) { best = nrm; bi = i; }
+        if (used) { nrm = -1; sel = -1; }
+        if (sel > best || (sel == best && i < bi)) { best = sel; bi = i; }
+        bestf = nrm > bestf ? nrm : bestf;
       }
       if (sizeof(T) == 4) {
         int dummy = 0;
         block_argmax(graw, dummy, s_av, s_ai);
       }
       block_argmax(best, bi, s_av, s_ai);
+      if (a.det_pivot) {
+        int dummy = 0;
+        block_argmax(bestf, dummy, s_av, s_ai);
+      } else {
+        bestf = best;
+      }
       // no usable row (all used or non-finite): stop without a new term
       if (!(best >= NT(0)) || bi < 0 || bi >= c) { fallback = true; break; }
-      if (best <= NT(1e-30) * s_lam2) { converged = true; break; }
+      if (bestf <= NT(1e-30) * s_lam2) { converged = true; break; }
       // single precision: a residual at the rounding level of the raw column
       // (32 units of roundoff) carries no information; the block is converged
-      if (sizeof(T) == 4 && best <= NT(3.6e-12) * graw) { converged = true; break; }
+      if (sizeof(T) == 4 && bestf <= NT(3.6e-12) * graw) { converged = true; break; }
       if (tid == 0) {
         const T* P = Ck + 9 * (int64_t)bi;
         double p[9];   // pivot determinant and inverse in FP64 in every form
@@ -226,10 +287,28 @@ __global__ __launch_bounds__(ACA_T) void k_aca(AcaArgs<T> a) {
       best = -1;
       bi = 0x7fffffff;
       double tp0 = 0, tp1 = 0, tp2 = 0;   // t_k = sum_j q_k(j) F_j (fused apply)
+      if (MF) {
+        for (int t0 = 32 * wv; t0 < q; t0 += 32 * NW) {
+          const int jj = t0 + (lane & 31);
+          const int jc = jj < q ? jj : t0;
+          float K[9];
+          mfma_entry(fr, a.kp.input_mode, xi0 - xsr[3 * jc], xi1 - xsr[3 * jc + 1],
+                     xi2 - xsr[3 * jc + 2], K);
+          if (jj < q && lane < 32)
+#pragma unroll
+            for (int e = 0; e < 9; ++e) Qk[9 * (int64_t)jj + e] = (T)K[e];
+        }
+        __syncthreads();
+      }
       for (int jj = tid; jj < q; jj += ACA_T) {
         T K[9];
-        kernel_entry<T>(a.kp, wl, (T)(xi0 - xsr[3 * jj]), (T)(xi1 - xsr[3 * jj + 1]),
-                        (T)(xi2 - xsr[3 * jj + 2]), K);
+        if (MF) {
+#pragma unroll
+          for (int e = 0; e < 9; ++e) K[e] = Qk[9 * (int64_t)jj + e];
+        } else {
+          kernel_entry<T>(a.kp, wl, (T)(xi0 - xsr[3 * jj]), (T)(xi1 - xsr[3 * jj + 1]),
+                          (T)(xi2 - xsr[3 * jj + 2]), K);
+        }
         for (int m = 0; m < k; ++m) {
           const T* qm = a.pool + s_off[m] + 9 * (int64_t)c + 9 * (int64_t)jj;
           T qv[9];
@@ -255,10 +334,11 @@ __global__ __launch_bounds__(ACA_T) void k_aca(AcaArgs<T> a) {
           tp1 += (double)K[3] * f0 + (double)K[4] * f1 + (double)K[5] * f2;
           tp2 += (double)K[6] * f0 + (double)K[7] * f1 + (double)K[8] * f2;
         }
+        NT sel = a.det_pivot ? det3<NT>(K) : nrm;
         bool used = false;
         for (int m = 0; m <= k; ++m) used |= (s_pj[m] == jj);
-        if (used) nrm = -1;
-        if (nrm > best || (nrm == best && jj < bi)) { best = nrm; bi = jj; }
+        if (used) sel = -1;
+        if (sel > best || (sel == best && jj < bi)) { best = sel; bi = jj; }
       }
       block_argmax(best, bi, s_av, s_ai);
       const int jn = (bi >= 0 && bi < q) ? bi : -1;   // -1 only when every column is used
@@ -338,7 +418,30 @@ __global__ __launch_bounds__(ACA_T) void k_aca(AcaArgs<T> a) {
     }
     if (!converged) fallback = true;
     __syncthreads();
-    if (fuse && fallback) {
+    if (fuse && fallback && MF) {
+      // dense evaluation of the block's rows (32-row MFMA tiles)
+      for (int t0 = 32 * wv; t0 < c; t0 += 32 * NW) {
+        const int i = t0 + (lane & 31);
+        const int ii = i < c ? i : t0;
+        const double x0 = xt[3 * ii], x1 = xt[3 * ii + 1], x2 = xt[3 * ii + 2];
+        double v0 = 0, v1 = 0, v2 = 0;
+        for (int jj = 0; jj < q; ++jj) {
+          float K[9];
+          mfma_entry(fr, a.kp.input_mode, x0 - xsr[3 * jj], x1 - xsr[3 * jj + 1],
+                     x2 - xsr[3 * jj + 2], K);
+          const T* f = a.Fs + 3 * ((int64_t)ns.x + jj);
+          v0 += (double)(K[0] * (float)f[0] + K[1] * (float)f[1] + K[2] * (float)f[2]);
+          v1 += (double)(K[3] * (float)f[0] + K[4] * (float)f[1] + K[5] * (float)f[2]);
+          v2 += (double)(K[6] * (float)f[0] + K[7] * (float)f[1] + K[8] * (float)f[2]);
+        }
+        if (i < c && lane < 32) {
+          ub[3 * i] = v0;
+          ub[3 * i + 1] = v1;
+          ub[3 * i + 2] = v2;
+        }
+      }
+    }
+    if (fuse && fallback && !MF) {
       // dense evaluation of the block's rows replaces the partial sum
       for (int i = tid; i < c; i += ACA_T) {
         const double x0 = xt[3 * i], x1 = xt[3 * i + 1], x2 = xt[3 * i + 2];
@@ -402,15 +505,19 @@ void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
   a.Fs = (const T*)Fs;
   a.ublk = ublk;
   a.uoff = uoff;
+  a.frags = k->pbf.as<uint4>();
+  a.det_pivot = lr->prec != HH_FP64;
   int grid = (int)std::min<int64_t>(b1 - b0, 4096);
   if (grid <= 0) return;
   const bool fp64norm = lr->prec != HH_FP32;
-#define LAUNCH(NT_, KIND_)                                                                  \
-  hipLaunchKernelGGL((k_aca<T, NT_, KIND_>), dim3(grid), dim3(ACA_T), 0, ctx->stream, a)
-  if (k->kind == KIND_MLP) {
-    if (fp64norm) LAUNCH(double, KIND_MLP); else LAUNCH(T, KIND_MLP);
+#define LAUNCH(NT_, KIND_, MF_)                                                             \
+  hipLaunchKernelGGL((k_aca<T, NT_, KIND_, MF_>), dim3(grid), dim3(ACA_T), 0, ctx->stream, a)
+  if (k->kind == KIND_MLP && lr->prec == HH_BF16) {
+    if constexpr (sizeof(T) == 4) LAUNCH(double, KIND_MLP, true);
+  } else if (k->kind == KIND_MLP) {
+    if (fp64norm) LAUNCH(double, KIND_MLP, false); else LAUNCH(T, KIND_MLP, false);
   } else {
-    if (fp64norm) LAUNCH(double, KIND_RPY); else LAUNCH(T, KIND_RPY);
+    if (fp64norm) LAUNCH(double, KIND_RPY, false); else LAUNCH(T, KIND_RPY, false);
   }
 #undef LAUNCH
   HIP_OK(hipGetLastError());

@@ -81,7 +81,7 @@ __global__ __launch_bounds__(T256) void k_far_t(const int2* __restrict__ G, int6
   }
 }
 
-template <class T, class TO, int KIND>
+template <class T, class TU, class TO, int KIND>
 __global__ __launch_bounds__(T256) void k_combine(
     int64_t n, const int32_t* __restrict__ perm, const int32_t* __restrict__ leaf_of,
     const int32_t* __restrict__ parent, const int4* __restrict__ nodes,
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(T256) void k_combine(
     const int32_t* __restrict__ rank, const int32_t* __restrict__ flag,
     const int64_t* __restrict__ fptr, const int64_t* __restrict__ toff,
     const T* __restrict__ pool, const double* __restrict__ tbuf, const double* __restrict__ xs,
-    const T* __restrict__ Fs, const T* __restrict__ Un, KParams kp, TO* __restrict__ U) {
+    const T* __restrict__ Fs, const TU* __restrict__ Un, KParams kp, TO* __restrict__ U) {
   __shared__ T wl[KIND == KIND_MLP ? MLP_NP : 1];
   if (KIND == KIND_MLP) {
     const T* w = (const T*)kp.w;
@@ -165,9 +165,9 @@ __global__ __launch_bounds__(T256) void k_far_gather(
   Uf[3 * s + 2] += u2;
 }
 
-template <class T, class TO>
+template <class T, class TU, class TO>
 __global__ __launch_bounds__(T256) void k_final(int64_t n, const int32_t* __restrict__ perm,
-                                                const T* __restrict__ Fs, const T* __restrict__ Un,
+                                                const T* __restrict__ Fs, const TU* __restrict__ Un,
                                                 const double* __restrict__ Uf, double alpha1,
                                                 TO* __restrict__ U) {
   int64_t s = (int64_t)blockIdx.x * T256 + threadIdx.x;
@@ -190,14 +190,14 @@ KParams make_kparams(hh_kernel k, bool fp64) {
   return kp;
 }
 
-template <class T, class TI, class TO>
+template <class T, class TI, class TO, class TU>
 void matvec_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kernel k, const void* F,
               void* U) {
   hipStream_t st = ctx->stream;
   const int64_t n = t->n;
   DevBuf Fs, Un;
   Fs.alloc(st, 3 * n * sizeof(T));
-  Un.alloc(st, 3 * n * sizeof(T));
+  Un.alloc(st, 3 * n * sizeof(TU));
   hipLaunchKernelGGL((k_gather_rows<TI, T>), dim3(nblk(n)), dim3(T256), 0, st, (const TI*)F,
                      t->perm.as<int32_t>(), n, Fs.as<T>());
   {
@@ -215,12 +215,12 @@ void matvec_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kernel k, cons
   }
   KParams kp = make_kparams(k, sizeof(T) == 8);
 #define COMBINE(KIND_)                                                                       \
-  hipLaunchKernelGGL((k_combine<T, TO, KIND_>), dim3(nblk(n)), dim3(T256), 0, st, n,          \
+  hipLaunchKernelGGL((k_combine<T, TU, TO, KIND_>), dim3(nblk(n)), dim3(T256), 0, st, n,      \
                      t->perm.as<int32_t>(), t->leaf_of.as<int32_t>(), t->parent.as<int32_t>(), \
                      t->nodes.as<int4>(), p->far_ptr.as<int32_t>(), p->G.as<int2>(),           \
                      lr->rank.as<int32_t>(), lr->flag.as<int32_t>(), lr->fptr.as<int64_t>(),   \
                      lr->toff.as<int64_t>(), lr->pool.as<T>(), lr->tbuf.as<double>(),          \
-                     t->xs.as<double>(), Fs.as<T>(), Un.as<T>(), kp, (TO*)U)
+                     t->xs.as<double>(), Fs.as<T>(), Un.as<TU>(), kp, (TO*)U)
   {
     PhaseTimer timer(ctx, HH_PHASE_COMBINE);
     if (k->kind == KIND_MLP) COMBINE(KIND_MLP); else COMBINE(KIND_RPY);
@@ -229,14 +229,14 @@ void matvec_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kernel k, cons
   HIP_OK(hipGetLastError());
 }
 
-template <class T, class TI, class TO>
+template <class T, class TI, class TO, class TU>
 void matvec_streamed_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kernel k,
                        const void* F, void* U) {
   hipStream_t st = ctx->stream;
   const int64_t n = t->n;
   DevBuf Fs, Un, Uf, counters;
   Fs.alloc(st, 3 * n * sizeof(T));
-  Un.alloc(st, 3 * n * sizeof(T));
+  Un.alloc(st, 3 * n * sizeof(TU));
   Uf.alloc(st, 3 * n * sizeof(double));
   hipLaunchKernelGGL((k_gather_rows<TI, T>), dim3(nblk(n)), dim3(T256), 0, st, (const TI*)F,
                      t->perm.as<int32_t>(), n, Fs.as<T>());
@@ -264,8 +264,8 @@ void matvec_streamed_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kerne
   }
   {
     PhaseTimer timer(ctx, HH_PHASE_COMBINE);
-    hipLaunchKernelGGL((k_final<T, TO>), dim3(nblk(n)), dim3(T256), 0, st, n,
-                       t->perm.as<int32_t>(), Fs.as<T>(), Un.as<T>(), Uf.as<double>(),
+    hipLaunchKernelGGL((k_final<T, TU, TO>), dim3(nblk(n)), dim3(T256), 0, st, n,
+                       t->perm.as<int32_t>(), Fs.as<T>(), Un.as<TU>(), Uf.as<double>(),
                        k->alpha1, (TO*)U);
   }
   HIP_OK(hipGetLastError());
@@ -313,19 +313,25 @@ hh_status hh_matvec(hh_ctx ctx, hh_tree tree, hh_part part, hh_lowrank lr, hh_ke
              "handles do not belong together");
   HH_REQUIRE(lr->prec == prec, HH_ERR_INVALID_ARG, "precision differs from the ACA build");
   HH_REQUIRE(lr->kern == kern, HH_ERR_INVALID_ARG, "kernel differs from the ACA build");
+  // <storage/kernel type, F type, U type, near-field row type>
+  const bool mfma = prec == HH_BF16 && kern->kind == KIND_MLP;
   if (lr->streamed) {
     if (prec == HH_FP64)
-      matvec_streamed_t<double, double, double>(ctx, tree, part, lr, kern, F, U);
+      matvec_streamed_t<double, double, double, double>(ctx, tree, part, lr, kern, F, U);
     else if (prec == HH_FP32)
-      matvec_streamed_t<float, float, float>(ctx, tree, part, lr, kern, F, U);
+      matvec_streamed_t<float, float, float, float>(ctx, tree, part, lr, kern, F, U);
+    else if (mfma)
+      matvec_streamed_t<float, float, double, double>(ctx, tree, part, lr, kern, F, U);
     else
-      matvec_streamed_t<float, float, double>(ctx, tree, part, lr, kern, F, U);
+      matvec_streamed_t<float, float, double, float>(ctx, tree, part, lr, kern, F, U);
   } else if (prec == HH_FP64) {
-    matvec_t<double, double, double>(ctx, tree, part, lr, kern, F, U);
+    matvec_t<double, double, double, double>(ctx, tree, part, lr, kern, F, U);
   } else if (prec == HH_FP32) {
-    matvec_t<float, float, float>(ctx, tree, part, lr, kern, F, U);
+    matvec_t<float, float, float, float>(ctx, tree, part, lr, kern, F, U);
+  } else if (mfma) {
+    matvec_t<float, float, double, double>(ctx, tree, part, lr, kern, F, U);
   } else {
-    matvec_t<float, float, double>(ctx, tree, part, lr, kern, F, U);
+    matvec_t<float, float, double, float>(ctx, tree, part, lr, kern, F, U);
   }
   HH_API_END(ctx)
 }

@@ -90,6 +90,85 @@ int64_t read_i64(hh_ctx ctx, const void* dev_ptr) {
   return ctx->pinned[0];
 }
 
+// BF16 round-to-nearest-even of a float, and back.
+static uint16_t bf16_rne(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+static float bf16_val(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
+}
+// w = hi + lo with hi, lo BF16
+static void bf16_split(double w, uint16_t& hi, uint16_t& lo) {
+  hi = bf16_rne((float)w);
+  lo = bf16_rne((float)(w - (double)bf16_val(hi)));
+}
+
+// K slot (8 h + u) of K step s <-> hidden feature, matching the MFMA result
+// register order (row 8 (v / 4) + 4 h + v % 4 of register v, v = 8 (s % 2) + u
+// of M tile s / 2).
+static int kslot_feature(int s, int h, int u) {
+  return 32 * (s / 2) + 16 * (s % 2) + 8 * (u / 4) + 4 * h + (u % 4);
+}
+
+// Fragment table of the BF16 MFMA MLP (layout in mlp_mfma.h): 16 bytes
+// (8 BF16) per lane and fragment.
+static std::vector<uint16_t> build_bf16_frags(const double* P) {
+  const int L1 = 0, L2 = L1 + 2 * 64, L3 = L2 + (2 * 4 * 2 + 2) * 64,
+            L4 = L3 + (2 * 4 * 2 + 2) * 64, TOTAL = L4 + (4 * 2 + 1) * 64;
+  std::vector<uint16_t> fr((size_t)TOTAL * 8, 0);
+  auto at = [&](int frag, int u) -> uint16_t& { return fr[(size_t)frag * 8 + u]; };
+  const double* W1 = P + OFF_W1;
+  const double* b1 = P + OFF_B1;
+  for (int mo = 0; mo < 2; ++mo)
+    for (int lane = 0; lane < 64; ++lane) {
+      int m = 32 * mo + (lane & 31), h = lane >> 5, f = L1 + mo * 64 + lane;
+      uint16_t wh[3], wl[3], bh, bl;
+      for (int d = 0; d < 3; ++d) bf16_split(W1[3 * m + d], wh[d], wl[d]);
+      bf16_split(b1[m], bh, bl);
+      if (h == 0) {
+        for (int d = 0; d < 3; ++d) { at(f, d) = wh[d]; at(f, 3 + d) = wh[d]; }
+        at(f, 6) = bh;
+        at(f, 7) = bl;
+      } else {
+        for (int d = 0; d < 3; ++d) at(f, d) = wl[d];
+      }
+    }
+  auto hidden = [&](int base, const double* W, const double* b, int nrow, int nmo) {
+    for (int mo = 0; mo < nmo; ++mo)
+      for (int lane = 0; lane < 64; ++lane) {
+        int m = 32 * mo + (lane & 31), h = lane >> 5;
+        for (int s = 0; s < 4; ++s)
+          for (int part = 0; part < 2; ++part) {
+            int f = base + ((mo * 4 + s) * 2 + part) * 64 + lane;
+            for (int u = 0; u < 8; ++u) {
+              if (m >= nrow) continue;
+              uint16_t hi, lo;
+              bf16_split(W[MLP_H * m + kslot_feature(s, h, u)], hi, lo);
+              at(f, u) = part == 0 ? hi : lo;
+            }
+          }
+        int fb = base + (nmo * 4 * 2) * 64 + mo * 64 + lane;
+        if (h == 0 && m < nrow) {
+          uint16_t hi, lo;
+          bf16_split(b[m], hi, lo);
+          at(fb, 0) = hi;
+          at(fb, 1) = lo;
+        }
+      }
+  };
+  hidden(L2, P + OFF_W2, P + OFF_B2, 64, 2);
+  hidden(L3, P + OFF_W3, P + OFF_B3, 64, 2);
+  hidden(L4, P + OFF_W4, P + OFF_B4, 9, 1);
+  return fr;
+}
+
 extern "C" {
 
 hh_status hh_ctx_create(int device, void* stream, hh_ctx* out) {
@@ -217,6 +296,10 @@ hh_status hh_kernel_create_mlp(hh_ctx ctx, const double* params, int input_mode,
     k->alpha1 = 1.0 / (6.0 * M_PI * mu * a);
     k->host_params.assign(params, params + MLP_NP);
     std::vector<float> p32(params, params + MLP_NP);
+    std::vector<uint16_t> fr = build_bf16_frags(params);
+    k->pbf.alloc(ctx->stream, fr.size() * sizeof(uint16_t));
+    HIP_OK(hipMemcpyAsync(k->pbf.p, fr.data(), fr.size() * sizeof(uint16_t),
+                          hipMemcpyHostToDevice, ctx->stream));
     k->p64.alloc(ctx->stream, MLP_NP * sizeof(double));
     k->p32.alloc(ctx->stream, MLP_NP * sizeof(float));
     HIP_OK(hipMemcpyAsync(k->p64.p, params, MLP_NP * sizeof(double), hipMemcpyHostToDevice,

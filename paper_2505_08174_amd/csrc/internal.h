@@ -120,6 +120,8 @@ struct hh_tree_s {
   DevBuf leaf_id;   // int32 [n_nodes] rank among leaves, -1 for internal
   DevBuf leaves;    // int32 [n_leaves] node id of each leaf, in order
   DevBuf leaf_of;   // int32 [n] leaf node of sorted position s
+  DevBuf units;     // int2 [n_units] (leaf rank, chunk of 32 targets), built lazily
+  int64_t n_units = 0;
 };
 
 // ------------------------------------------------------------ the partition
@@ -183,5 +185,7 @@ void radix_sort_u64(hh_ctx ctx, uint64_t* keys, uint32_t* vals, int64_t n, int b
 // Near-field, ACA, far-field and combine launches (near.hip, aca.hip, apply.hip).
 void launch_near(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, int prec, const void* F,
                  void* Unear);
+void launch_near_bf16(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void* Fs, void* Un);
+void ensure_units(hh_ctx ctx, hh_tree t);
 void launch_aca(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr, double eps,
                 int32_t l_max, int64_t* pool_top_dev);

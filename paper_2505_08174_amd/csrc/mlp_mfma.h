@@ -1,0 +1,135 @@
+// The seeded kernel MLP (3 -> 64 -> 64 -> 64 -> 9, tanh) on BF16 MFMA
+// (v_mfma_f32_32x32x16_bf16, FP32 accumulation) for one wave-tile of 32 pairs.
+//
+// Lane l works on pair p = l % 32; lanes l and l + 32 hold the same pair and
+// split the K dimension of every product (K slots 8 h .. 8 h + 7, h = l / 32).
+// Hidden layers are computed transposed, H^T[64 x 32] = W[64 x 64] H_in^T, so
+// the pairs are the MFMA columns. An MFMA result register v of lane l holds
+// row 8 (v / 4) + 4 h + v % 4 of column p; the next layer's K index is
+// permuted to exactly that order (the weights are stored pre-permuted), so a
+// layer's tanh output is the next layer's B operand without any data motion:
+// K step s (features 16 s .. 16 s + 15) takes result registers 8 (s % 2) ..
+// 8 (s % 2) + 7 of M tile s / 2.
+//
+// Precision: every weight W is stored as W_hi + W_lo (two BF16 numbers) and
+// multiplied in two MFMAs, which removes the systematic error of rounding
+// the weights to BF16; activations are rounded to BF16 once (near field) or
+// carried as BF16 hi + lo with a third MFMA per K step (ACA samples, whose
+// error must stay far below the cross-approximation tolerance). Layer 1 takes
+// the input v = v_hi + v_lo split the same way, with the bias in spare K
+// slots (K = 16: v_hi W_hi, v_lo W_hi, b_hi, b_lo, v_hi W_lo). The biases of
+// layers 2-4 enter through one extra K step whose B operand is the constant
+// column (1, 1, 0, ...). Accumulation is FP32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "devmath.h"
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Fragment table (16 bytes per lane and fragment) in LDS.
+#define FR_L1 0                                // [mo 2][lane 64]
+#define FR_L2 (FR_L1 + 2 * 64)                 // [mo 2][s 4][part 2][lane]; bias [mo 2][lane]
+#define FR_L3 (FR_L2 + (2 * 4 * 2 + 2) * 64)
+#define FR_L4 (FR_L3 + (2 * 4 * 2 + 2) * 64)   // [s 4][part 2][lane]; bias [lane]
+#define FR_TOTAL (FR_L4 + (4 * 2 + 1) * 64)
+#define FR_BYTES (FR_TOTAL * 16)
+
+__device__ __forceinline__ f32x16 mfma_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// tanh of 8 consecutive result registers -> one BF16 B operand (and, for
+// the accurate tile, the BF16 remainder t - hi as a second operand)
+template <bool ACC>
+__device__ __forceinline__ void act8(const f32x16& a, int base, bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    float t = hh_tanh(a[base + u]);
+    hi[u] = (__bf16)t;
+    if (ACC) lo[u] = (__bf16)(t - (float)hi[u]);
+  }
+}
+
+// One hidden layer (64 -> 64): B[4] in, B[4] out (after tanh). ACC adds the
+// products of the activation remainders (W_hi a_lo), for samples whose error
+// must stay far below the cross-approximation tolerance.
+template <bool ACC>
+__device__ __forceinline__ void hidden_layer(const bf16x8* __restrict__ fr, int base, int lane,
+                                             const bf16x8 (&B)[4], const bf16x8 (&Bl)[4],
+                                             const bf16x8& Bone, bf16x8 (&Bo)[4],
+                                             bf16x8 (&Bol)[4]) {
+#pragma unroll
+  for (int mo = 0; mo < 2; ++mo) {
+    f32x16 acc = {};
+    acc = mfma_bf16(fr[base + (2 * 4 * 2) * 64 + mo * 64 + lane], Bone, acc);   // bias
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const bf16x8 wh = fr[base + ((mo * 4 + s) * 2 + 0) * 64 + lane];
+      acc = mfma_bf16(wh, B[s], acc);
+      acc = mfma_bf16(fr[base + ((mo * 4 + s) * 2 + 1) * 64 + lane], B[s], acc);
+      if (ACC) acc = mfma_bf16(wh, Bl[s], acc);
+    }
+    act8<ACC>(acc, 0, Bo[2 * mo], Bol[2 * mo]);
+    act8<ACC>(acc, 8, Bo[2 * mo + 1], Bol[2 * mo + 1]);
+  }
+}
+
+// Raw outputs o[0..8] of the MLP at input (v0, v1, v2) for this lane's pair.
+// Must be called by all 64 lanes of the wave with lanes l and l+32 holding
+// the same input. ACC = false: activations rounded to BF16 once (relative
+// error ~1e-4 of a sample); ACC = true: activations carried as BF16 hi + lo
+// (~3e-6), used where samples must resolve a 1e-4 cross-approximation.
+template <bool ACC>
+__device__ __forceinline__ void mlp_tile_bf16(const bf16x8* __restrict__ fr, float v0, float v1,
+                                              float v2, float o[9]) {
+  const int lane = threadIdx.x & 63;
+  const bool h1 = lane >= 32;
+  const __bf16 z = (__bf16)0.0f, one = (__bf16)1.0f;
+  // layer 1 input column: K slots (v_hi, v_lo, 1, 1 | v_hi, 0...)
+  __bf16 vh0 = (__bf16)v0, vh1 = (__bf16)v1, vh2 = (__bf16)v2;
+  __bf16 vl0 = (__bf16)(v0 - (float)vh0), vl1 = (__bf16)(v1 - (float)vh1),
+         vl2 = (__bf16)(v2 - (float)vh2);
+  bf16x8 b1;
+  b1[0] = vh0; b1[1] = vh1; b1[2] = vh2;
+  b1[3] = h1 ? z : vl0; b1[4] = h1 ? z : vl1; b1[5] = h1 ? z : vl2;
+  b1[6] = h1 ? z : one; b1[7] = h1 ? z : one;
+  bf16x8 Bone;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) Bone[u] = (!h1 && u < 2) ? one : z;
+  bf16x8 B[4], Bn[4], Bl[4], Bnl[4];
+#pragma unroll
+  for (int mo = 0; mo < 2; ++mo) {
+    f32x16 acc = {};
+    acc = mfma_bf16(fr[FR_L1 + mo * 64 + lane], b1, acc);
+    act8<ACC>(acc, 0, B[2 * mo], Bl[2 * mo]);
+    act8<ACC>(acc, 8, B[2 * mo + 1], Bl[2 * mo + 1]);
+  }
+  hidden_layer<ACC>(fr, FR_L2, lane, B, Bl, Bone, Bn, Bnl);
+  hidden_layer<ACC>(fr, FR_L3, lane, Bn, Bnl, Bone, B, Bl);
+  f32x16 acc = {};
+  acc = mfma_bf16(fr[FR_L4 + (4 * 2) * 64 + lane], Bone, acc);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const bf16x8 wh = fr[FR_L4 + (s * 2 + 0) * 64 + lane];
+    acc = mfma_bf16(wh, B[s], acc);
+    acc = mfma_bf16(fr[FR_L4 + (s * 2 + 1) * 64 + lane], B[s], acc);
+    if (ACC) acc = mfma_bf16(wh, Bl[s], acc);
+  }
+  // rows 0-3 and 8 live in lanes 0-31 (registers 0-3, 4); rows 4-7 in 32-63
+  float t0 = __shfl_xor(acc[0], 32, 64), t1 = __shfl_xor(acc[1], 32, 64);
+  float t2 = __shfl_xor(acc[2], 32, 64), t3 = __shfl_xor(acc[3], 32, 64);
+  float t4 = __shfl_xor(acc[4], 32, 64);
+  o[0] = h1 ? t0 : acc[0]; o[1] = h1 ? t1 : acc[1]; o[2] = h1 ? t2 : acc[2]; o[3] = h1 ? t3 : acc[3];
+  o[4] = h1 ? acc[0] : t0; o[5] = h1 ? acc[1] : t1; o[6] = h1 ? acc[2] : t2; o[7] = h1 ? acc[3] : t3;
+  o[8] = h1 ? t4 : acc[4];
+}
+
+// Stage the fragment table (global -> LDS) by the whole workgroup.
+__device__ __forceinline__ void stage_frags(bf16x8* __restrict__ lds, const uint4* __restrict__ g,
+                                            int nthreads) {
+  uint4* d = reinterpret_cast<uint4*>(lds);
+  for (int i = threadIdx.x; i < FR_TOTAL; i += nthreads) d[i] = g[i];
+}

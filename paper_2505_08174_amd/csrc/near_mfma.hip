@@ -1,0 +1,138 @@
+// Near field with the seeded MLP kernel on BF16 MFMA (the BF16 form).
+//
+// Work unit = 32 consecutive targets of one leaf tau (one wave). The wave
+// walks every source j of every near leaf sigma of tau (uniform across the
+// wave, so x_j and F_j come through scalar loads) and evaluates the 32 pairs
+// (i, j) as one MFMA tile; each lane accumulates K(x_i - x_j) F_j for its own
+// target in FP64 (owner computes, no reduction, no atomics). Four units per
+// workgroup share the weight fragments staged in LDS.
+#include "internal.h"
+#include "mlp_mfma.h"
+
+#define T256_UNITS 256
+
+namespace {
+
+constexpr int NB_T = 256;
+
+__global__ __launch_bounds__(T256_UNITS) void k_units_count(const int32_t* __restrict__ leaves,
+                                                            int64_t nl,
+                                                            const int4* __restrict__ nodes,
+                                                            int64_t* __restrict__ cnt) {
+  int64_t l = (int64_t)blockIdx.x * T256_UNITS + threadIdx.x;
+  if (l > nl) return;
+  if (l == nl) { cnt[nl] = 0; return; }
+  int4 nd = nodes[leaves[l]];
+  cnt[l] = (nd.y - nd.x + 31) / 32;
+}
+
+__global__ __launch_bounds__(T256_UNITS) void k_units_fill(const int64_t* __restrict__ cnt,
+                                                           const int64_t* __restrict__ pos,
+                                                           int64_t nl, int2* __restrict__ units) {
+  int64_t l = (int64_t)blockIdx.x * T256_UNITS + threadIdx.x;
+  if (l >= nl) return;
+  for (int64_t c = 0; c < cnt[l]; ++c) units[pos[l] + c] = make_int2((int)l, (int)c);
+}
+
+struct NearB {
+  const uint4* frags;
+  const int4* nodes;
+  const int32_t* leaves;
+  const int32_t* near_ptr;
+  const int2* H;
+  const int2* units;
+  int64_t n_units;
+  const double* xs;
+  const float* Fs;
+  double* Un;
+  int input_mode;
+};
+
+__global__ __launch_bounds__(NB_T) void k_near_bf16(NearB a) {
+  __shared__ bf16x8 fr[FR_TOTAL];
+  stage_frags(fr, a.frags, NB_T);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t unit = (int64_t)blockIdx.x * (NB_T / 64) + w;
+  if (unit >= a.n_units) return;
+  const int2 un = a.units[unit];
+  const int4 nt = a.nodes[a.leaves[un.x]];
+  const int i = nt.x + 32 * un.y + (lane & 31);
+  const bool act = i < nt.y;
+  const int ii = act ? i : nt.x;
+  const double xi0 = a.xs[3 * (int64_t)ii], xi1 = a.xs[3 * (int64_t)ii + 1],
+               xi2 = a.xs[3 * (int64_t)ii + 2];
+  const bool dir = a.input_mode == HH_MLP_INPUT_DIRECTION;
+  const float c16 = (float)(1.0 / (16.0 * HH_PI));
+  double u0 = 0, u1 = 0, u2 = 0;
+  const int p0 = a.near_ptr[un.x], p1 = a.near_ptr[un.x + 1];
+  for (int p = p0; p < p1; ++p) {
+    const int4 ns = a.nodes[a.H[p].y];
+    for (int j = ns.x; j < ns.y; ++j) {
+      float rx = (float)(xi0 - a.xs[3 * (int64_t)j]);
+      float ry = (float)(xi1 - a.xs[3 * (int64_t)j + 1]);
+      float rz = (float)(xi2 - a.xs[3 * (int64_t)j + 2]);
+      const bool skip = (j == ii) || !act;
+      if (j == ii) { rx = 1.0f; ry = 0.0f; rz = 0.0f; }
+      const float rs = hh_rsqrt(rx * rx + ry * ry + rz * rz);
+      float o[9];
+      if (dir)
+        mlp_tile_bf16<false>(fr, rx * rs, ry * rs, rz * rs, o);
+      else
+        mlp_tile_bf16<false>(fr, rx, ry, rz, o);
+      const float sc = skip ? 0.0f : rs * c16;
+      const float f0 = a.Fs[3 * (int64_t)j], f1 = a.Fs[3 * (int64_t)j + 1],
+                  f2 = a.Fs[3 * (int64_t)j + 2];
+      u0 += (double)(sc * (2.0f * o[0] * f0 + (o[1] + o[3]) * f1 + (o[2] + o[6]) * f2));
+      u1 += (double)(sc * ((o[3] + o[1]) * f0 + 2.0f * o[4] * f1 + (o[5] + o[7]) * f2));
+      u2 += (double)(sc * ((o[6] + o[2]) * f0 + (o[7] + o[5]) * f1 + 2.0f * o[8] * f2));
+    }
+  }
+  if (act && lane < 32) {
+    a.Un[3 * (int64_t)i] = u0;
+    a.Un[3 * (int64_t)i + 1] = u1;
+    a.Un[3 * (int64_t)i + 2] = u2;
+  }
+}
+
+}  // namespace
+
+// Work units (leaf rank, chunk of 32 targets), built once per tree.
+void ensure_units(hh_ctx ctx, hh_tree t) {
+  if (t->n_units > 0) return;
+  hipStream_t st = ctx->stream;
+  int64_t nl = t->n_leaves;
+  DevBuf cnt, pos;
+  cnt.alloc(st, (nl + 1) * sizeof(int64_t));
+  pos.alloc(st, (nl + 1) * sizeof(int64_t));
+  unsigned g = (unsigned)((nl + 1 + T256_UNITS - 1) / T256_UNITS);
+  hipLaunchKernelGGL(k_units_count, dim3(g), dim3(T256_UNITS), 0, st, t->leaves.as<int32_t>(), nl,
+                     t->nodes.as<int4>(), cnt.as<int64_t>());
+  scan_exclusive_i64(ctx, cnt.as<int64_t>(), pos.as<int64_t>(), nl + 1);
+  int64_t nu = read_i64(ctx, pos.as<int64_t>() + nl);
+  t->units.alloc(st, std::max<int64_t>(1, nu) * sizeof(int2));
+  hipLaunchKernelGGL(k_units_fill, dim3(g), dim3(T256_UNITS), 0, st, cnt.as<int64_t>(),
+                     pos.as<int64_t>(), nl, t->units.as<int2>());
+  HIP_OK(hipGetLastError());
+  t->n_units = nu;
+}
+
+void launch_near_bf16(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void* Fs, void* Un) {
+  HH_REQUIRE(k->kind == KIND_MLP, HH_ERR_INVALID_ARG, "the BF16 form needs the MLP kernel");
+  ensure_units(ctx, t);
+  NearB a;
+  a.frags = k->pbf.as<uint4>();
+  a.nodes = t->nodes.as<int4>();
+  a.leaves = t->leaves.as<int32_t>();
+  a.near_ptr = p->near_ptr.as<int32_t>();
+  a.H = p->H.as<int2>();
+  a.units = t->units.as<int2>();
+  a.n_units = t->n_units;
+  a.xs = t->xs.as<double>();
+  a.Fs = (const float*)Fs;
+  a.Un = (double*)Un;
+  a.input_mode = k->input_mode;
+  unsigned grid = (unsigned)((t->n_units + 3) / 4);
+  hipLaunchKernelGGL(k_near_bf16, dim3(grid), dim3(NB_T), 0, ctx->stream, a);
+  HIP_OK(hipGetLastError());
+}

@@ -21,11 +21,12 @@ def _sep_block(c, q, r, seed):
     return G
 
 
+@pytest.mark.parametrize("pivot", ["frobenius", "determinant"])
 @pytest.mark.parametrize("r", [1, 2, 5])
-def test_exact_rank_recovered(r):
+def test_exact_rank_recovered(r, pivot):
     c, q = 40, 33
     G = _sep_block(c, q, r, 30 + r)
-    res = aca.aca_entries(lambda j: G[:, j], lambda i: G[i, :], c, q, 1e-10, 20)
+    res = aca.aca_entries(lambda j: G[:, j], lambda i: G[i, :], c, q, 1e-10, 20, pivot=pivot)
     assert res.converged
     assert res.rank in (r, r + 1)
     err = np.linalg.norm(aca.lowrank_dense(res) - G) / np.linalg.norm(G)
@@ -43,21 +44,23 @@ def _rpy_block(seed=0):
     return out
 
 
-def test_zero_tolerance_interpolates_block():
+@pytest.mark.parametrize("pivot", ["frobenius", "determinant"])
+def test_zero_tolerance_interpolates_block(pivot):
     kern = kernels.Kernel("rpy")
     Xt, Xs = _rpy_block()[0]
     Xt, Xs = Xt[:12], Xs[:9]
-    res = aca.aca_block(kern, Xt, Xs, 0.0, 100)
+    res = aca.aca_block(kern, Xt, Xs, 0.0, 100, pivot=pivot)
     G = kern(Xt[:, None] - Xs[None])
     assert res.converged and res.rank == 9
     assert np.linalg.norm(aca.lowrank_dense(res) - G) <= 1e-10 * np.linalg.norm(G)
 
 
-def test_residual_zero_on_pivots_and_norms_match():
+@pytest.mark.parametrize("pivot", ["frobenius", "determinant"])
+def test_residual_zero_on_pivots_and_norms_match(pivot):
     kern = kernels.Kernel("rpy")
     Xt, Xs = _rpy_block()[3]
     G = kern(Xt[:, None] - Xs[None])
-    res = aca.aca_block(kern, Xt, Xs, 1e-8, 30)
+    res = aca.aca_block(kern, Xt, Xs, 1e-8, 30, pivot=pivot)
     gnorm = np.linalg.norm(G)
     for k in range(1, res.rank + 1):
         approx = np.einsum("kiab,kjbc->ijac", res.C[:k], res.Q[:k])
@@ -70,8 +73,9 @@ def test_residual_zero_on_pivots_and_norms_match():
         assert res.lam2[k - 1] == pytest.approx(np.sum(approx * approx), rel=1e-10)
 
 
+@pytest.mark.parametrize("pivot", ["frobenius", "determinant"])
 @pytest.mark.parametrize("kind,eps", [("rpy", 1e-4), ("rpy", 1e-6), ("mlp", 1e-4)])
-def test_block_error_within_ten_zeta(kind, eps):
+def test_block_error_within_ten_zeta(kind, eps, pivot):
     if kind == "rpy":
         kern = kernels.Kernel("rpy")
     else:
@@ -79,7 +83,19 @@ def test_block_error_within_ten_zeta(kind, eps):
         kern = kernels.Kernel("mlp", kernels.MLP(Ws, bs))
     for Xt, Xs in _rpy_block(1):
         G = kern(Xt[:, None] - Xs[None])
-        res = aca.aca_block(kern, Xt, Xs, eps, 48)
+        res = aca.aca_block(kern, Xt, Xs, eps, 48, pivot=pivot)
         assert res.converged
         err = np.linalg.norm(aca.lowrank_dense(res) - G) / np.linalg.norm(G)
         assert err <= 10 * eps
+
+
+def test_determinant_pivot_prefers_well_conditioned_entries():
+    # two candidate rows: a large nearly singular entry and a smaller regular
+    # one; the Frobenius rule takes the first, the determinant rule the second
+    big = np.diag([10.0, 10.0, 1e-9])
+    small = np.eye(3)
+    G = np.stack([np.stack([big, 2 * big]), np.stack([small, 3 * small])])   # [2, 2, 3, 3]
+    rf = aca.aca_entries(lambda j: G[:, j], lambda i: G[i, :], 2, 2, 0.0, 1, pivot="frobenius")
+    rd = aca.aca_entries(lambda j: G[:, j], lambda i: G[i, :], 2, 2, 0.0, 1, pivot="determinant")
+    assert rd.rank == 1 and rd.piv_i[0] == 1
+    assert rf.rank == 0 or rf.piv_i[0] == 0
