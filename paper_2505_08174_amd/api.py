@@ -225,6 +225,64 @@ def matvec(ctx: Context, tree: Tree, part: Partition, lr: LowRank, kern: Kernel,
     return U
 
 
+def matvec_backward(ctx: Context, tree: Tree, part: Partition, lr: LowRank, kern: Kernel,
+                    F: torch.Tensor, dU: torch.Tensor, prec="fp64", want=("F", "X", "theta")):
+    """(dF, dX, dtheta) of L = sum dU . U with the structure frozen (None where
+    not requested). dtheta is the packed FP64 parameter vector."""
+    p = _prec(prec)
+    n = tree.info()[0]
+    F, dU = F.contiguous(), dU.contiguous()
+    assert F.dtype == F_DTYPE[p] and dU.dtype == U_DTYPE[p] and F.shape == dU.shape == (n, 3)
+    dF = torch.empty_like(F) if "F" in want else None
+    dX = torch.empty((n, 3), dtype=torch.float64, device=F.device) if "X" in want else None
+    dth = (torch.zeros(L.HH_MLP_NPARAM, dtype=torch.float64, device=F.device)
+           if "theta" in want else None)
+    nul = C.c_void_p(0)
+    ctx.check(L.load().hh_matvec_backward(
+        ctx.h, tree.h, part.h, lr.h, kern.h, p, _ptr(F), _ptr(dU),
+        _ptr(dF) if dF is not None else nul, _ptr(dX) if dX is not None else nul,
+        _ptr(dth) if dth is not None else nul))
+    return dF, dX, dth
+
+
+class HMatvecFn(torch.autograd.Function):
+    """U = M_H(X; theta) F with the H-matrix rebuilt from X in the forward and
+    its structure frozen for the backward. theta: packed FP64 MLP parameters
+    (a CPU tensor). cfg: dict(c_leaf, eta, eps, prec, l_max, input_mode)."""
+
+    @staticmethod
+    def forward(fctx, X, F, theta, ctx, cfg):
+        kern = Kernel.mlp(ctx, theta.detach().cpu().double().numpy(), cfg.get("input_mode", "direction"))
+        hm = HMatrix(ctx, X.detach(), kern, cfg.get("c_leaf", 64), cfg.get("eta", 1.0),
+                     cfg.get("eps", 1e-6), cfg.get("prec", "fp64"), cfg.get("l_max", 48))
+        U = hm @ F.detach()
+        fctx.hm = hm
+        fctx.save_for_backward(F)
+        fctx.theta_device = theta.device
+        return U
+
+    @staticmethod
+    def backward(fctx, gU):
+        (F,) = fctx.saved_tensors
+        hm = fctx.hm
+        want = []
+        if fctx.needs_input_grad[1]:
+            want.append("F")
+        if fctx.needs_input_grad[0]:
+            want.append("X")
+        if fctx.needs_input_grad[2]:
+            want.append("theta")
+        dF, dX, dth = matvec_backward(hm.ctx, hm.tree, hm.part, hm.lr, hm.kern, F,
+                                      gU.contiguous().to(U_DTYPE[hm.prec]), hm.prec, tuple(want))
+        if dth is not None:
+            dth = dth.to(fctx.theta_device)
+        return dX, dF, dth, None, None
+
+
+def hmatvec_autograd(ctx, X, F, theta, **cfg):
+    return HMatvecFn.apply(X, F, theta, ctx, cfg)
+
+
 class HMatrix:
     """Tree + partition + factors for one configuration X (rebuilt when X moves)."""
 

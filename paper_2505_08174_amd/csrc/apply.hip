@@ -336,16 +336,6 @@ hh_status hh_matvec(hh_ctx ctx, hh_tree tree, hh_part part, hh_lowrank lr, hh_ke
   HH_API_END(ctx)
 }
 
-hh_status hh_matvec_backward(hh_ctx ctx, hh_tree tree, hh_part part, hh_lowrank lr,
-                             hh_kernel kern, hh_precision prec, const void* F, const void* dU,
-                             void* dF, double* dX, double* dparams) {
-  HH_API_BEGIN(ctx)
-  (void)tree; (void)part; (void)lr; (void)kern; (void)prec; (void)F; (void)dU; (void)dF;
-  (void)dX; (void)dparams;
-  throw hh_error{HH_ERR_INVALID_ARG, "hh_matvec_backward: not available in this build"};
-  HH_API_END(ctx)
-}
-
 void hh_lowrank_free(hh_lowrank l) { delete l; }
 
 hh_status hh_lowrank_info(hh_lowrank l, int64_t* n_blocks, int64_t* rank_sum,

@@ -187,5 +187,7 @@ void launch_near(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, int prec, const 
                  void* Unear);
 void launch_near_bf16(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void* Fs, void* Un);
 void ensure_units(hh_ctx ctx, hh_tree t);
+void launch_near_neg(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, int prec, const void* Vs,
+                     void* out);
 void launch_aca(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr, double eps,
                 int32_t l_max, int64_t* pool_top_dev);

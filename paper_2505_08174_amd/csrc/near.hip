@@ -25,6 +25,7 @@ struct NearArgs {
   T* Un;
   KParams kp;
   int64_t n_leaves;
+  double sgn;   // +1: K(x_i - x_j); -1: K(x_j - x_i) (transposed product)
 };
 
 template <class T, int KIND>
@@ -58,7 +59,8 @@ __global__ __launch_bounds__(NEAR_T) void k_near_valu(NearArgs<T> a) {
         if (act) {
           for (int jj = 0; jj < cnt; ++jj) {
             if (jb + jj == i) continue;
-            T rx = (T)(xi0 - sx[3 * jj]), ry = (T)(xi1 - sx[3 * jj + 1]), rz = (T)(xi2 - sx[3 * jj + 2]);
+            T rx = (T)(a.sgn * (xi0 - sx[3 * jj])), ry = (T)(a.sgn * (xi1 - sx[3 * jj + 1])),
+              rz = (T)(a.sgn * (xi2 - sx[3 * jj + 2]));
             T K[9];
             kernel_entry<T>(a.kp, wl, rx, ry, rz, K);
             T f0 = sf[3 * jj], f1 = sf[3 * jj + 1], f2 = sf[3 * jj + 2];
@@ -78,8 +80,10 @@ __global__ __launch_bounds__(NEAR_T) void k_near_valu(NearArgs<T> a) {
 }
 
 template <class T>
-void launch_near_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void* Fs, void* Un) {
+void launch_near_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void* Fs, void* Un,
+                   double sgn = 1.0) {
   NearArgs<T> a;
+  a.sgn = sgn;
   a.nodes = t->nodes.as<int4>();
   a.leaves = t->leaves.as<int32_t>();
   a.near_ptr = p->near_ptr.as<int32_t>();
@@ -105,6 +109,16 @@ void launch_near_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void* Fs
 }
 
 }  // namespace
+
+// Near field with the displacement reversed: sum_j K(x_j - x_i) v_j, which is
+// the transposed near product (K entries are symmetric 3x3 matrices).
+void launch_near_neg(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, int prec, const void* Vs,
+                     void* out) {
+  if (prec == HH_FP64)
+    launch_near_t<double>(ctx, t, p, k, Vs, out, -1.0);
+  else
+    launch_near_t<float>(ctx, t, p, k, Vs, out, -1.0);
+}
 
 void launch_near(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, int prec, const void* Fs,
                  void* Un) {
