@@ -123,6 +123,18 @@ void hh_kernel_free(hh_kernel k);
  * Syncs. */
 hh_status hh_build_tree(hh_ctx ctx, const double* X, int64_t n, int32_t c_leaf, hh_tree* out);
 
+/* Many independent systems in one tree (the batched form): X is the
+ * concatenation of n_sys systems, offsets (host, n_sys + 1 values, offsets[0]
+ * = 0, strictly increasing) delimit them. Each system gets its own root box
+ * and its own subtree, identical to hh_build_tree on that system alone (node
+ * ids and particle positions shifted by the systems before it); hh_partition
+ * then starts Algorithm 1 at (root_s, root_s) for every system, so no block
+ * couples two systems, and hh_aca_build / hh_matvec / hh_matvec_backward
+ * process all systems' blocks in the same launches. Errors as hh_build_tree,
+ * plus an empty system -> HH_ERR_INVALID_ARG. Syncs. */
+hh_status hh_build_tree_batch(hh_ctx ctx, const double* X, const int64_t* offsets,
+                              int32_t n_sys, int32_t c_leaf, hh_tree* out);
+
 /* Block partition (Algorithm 1) with the admissibility test Eq. (7) on tight
  * bounding boxes of the member centres: admissible iff dist^2 > 0 and
  * max(diam_tau^2, diam_sigma^2) <= eta^2 dist^2. eta > 0. dense_mode != 0

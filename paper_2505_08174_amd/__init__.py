@@ -6,6 +6,7 @@ call does, and raises if the library has not been built.
 """
 from ._lib import HHError, load  # noqa: F401
 from .api import (  # noqa: F401
-    Context, Kernel, Tree, Partition, LowRank, HMatrix, build_tree, partition, aca_build, matvec,
+    Context, Kernel, Tree, Partition, LowRank, HMatrix, build_tree, build_tree_batch, partition,
+    aca_build, matvec,
     hmatvec, pack_mlp, PRECISION, matvec_backward, HMatvecFn, hmatvec_autograd,
 )

@@ -199,6 +199,18 @@ def build_tree(ctx: Context, X: torch.Tensor, c_leaf: int) -> Tree:
     return Tree(ctx, h)
 
 
+def build_tree_batch(ctx: Context, X: torch.Tensor, offsets, c_leaf: int) -> Tree:
+    """One tree over several independent systems (concatenated in X)."""
+    assert X.is_cuda and X.dtype == torch.float64 and X.dim() == 2 and X.shape[1] == 3
+    X = X.contiguous()
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    assert off[0] == 0 and off[-1] == X.shape[0]
+    h = C.c_void_p()
+    ctx.check(L.load().hh_build_tree_batch(ctx.h, _ptr(X), off.ctypes.data_as(C.POINTER(C.c_int64)),
+                                           len(off) - 1, int(c_leaf), C.byref(h)))
+    return Tree(ctx, h)
+
+
 def partition(ctx: Context, tree: Tree, eta: float = 1.0, dense_mode: bool = False) -> Partition:
     h = C.c_void_p()
     ctx.check(L.load().hh_partition(ctx.h, tree.h, float(eta), int(bool(dense_mode)), C.byref(h)))
@@ -284,12 +296,16 @@ def hmatvec_autograd(ctx, X, F, theta, **cfg):
 
 
 class HMatrix:
-    """Tree + partition + factors for one configuration X (rebuilt when X moves)."""
+    """Tree + partition + factors for one configuration X (rebuilt when X moves).
+    offsets: optional particle offsets of several independent systems in X."""
 
     def __init__(self, ctx, X, kern, c_leaf=64, eta=1.0, eps=1e-6, prec="fp64", l_max=48,
-                 dense_mode=False):
+                 dense_mode=False, offsets=None):
         self.ctx, self.kern, self.prec = ctx, kern, _prec(prec)
-        self.tree = build_tree(ctx, X, c_leaf)
+        if offsets is None:
+            self.tree = build_tree(ctx, X, c_leaf)
+        else:
+            self.tree = build_tree_batch(ctx, X, offsets, c_leaf)
         self.part = partition(ctx, self.tree, eta, dense_mode)
         self.lr = aca_build(ctx, self.tree, self.part, kern, self.prec, eps, l_max)
 

@@ -122,6 +122,10 @@ struct hh_tree_s {
   DevBuf leaf_of;   // int32 [n] leaf node of sorted position s
   DevBuf units;     // int2 [n_units] (leaf rank, chunk of 32 targets), built lazily
   int64_t n_units = 0;
+  int n_sys = 1;                    // independent systems (batched build)
+  std::vector<int64_t> offs_host;   // particle offsets of the systems [n_sys+1]
+  DevBuf offs;                      // same, on the device
+  DevBuf roots;                     // int32 [n_sys] root node of each system
 };
 
 // ------------------------------------------------------------ the partition

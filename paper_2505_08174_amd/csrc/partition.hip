@@ -146,6 +146,12 @@ __global__ __launch_bounds__(T256) void k_pair_sizes(const int2* __restrict__ L,
   if ((threadIdx.x & 63) == 0 && v) atomicAdd(sum, v);
 }
 
+__global__ void k_roots_frontier(const int32_t* __restrict__ roots, int nsys,
+                                 int2* __restrict__ fr) {
+  int s = blockIdx.x * 256 + threadIdx.x;
+  if (s < nsys) fr[s] = make_int2(roots[s], roots[s]);
+}
+
 }  // namespace
 
 static void sort_pairs(hh_ctx ctx, DevBuf& L, int64_t m, int nb) {
@@ -181,11 +187,13 @@ hh_status hh_partition(hh_ctx ctx, hh_tree tree, double eta, int dense_mode, hh_
     double eta2 = eta * eta;
     std::vector<DevBuf*> gl, hl;
     std::vector<int64_t> gn, hn;
+    // Algorithm 1 starts at (I, I) for every independent system
     DevBuf* fr = new DevBuf();
-    fr->alloc(st, sizeof(int2));
-    int2 root = make_int2(0, 0);
-    HIP_OK(hipMemcpyAsync(fr->p, &root, sizeof(int2), hipMemcpyHostToDevice, st));
-    int64_t nf = 1;
+    const int nsys = tree->n_sys;
+    fr->alloc(st, nsys * sizeof(int2));
+    hipLaunchKernelGGL(k_roots_frontier, dim3((nsys + 255) / 256), dim3(256), 0, st,
+                       tree->roots.as<int32_t>(), nsys, fr->as<int2>());
+    int64_t nf = nsys;
     int64_t totG = 0, totH = 0;
     try {
       for (int level = 0; nf > 0; ++level) {

@@ -20,54 +20,87 @@ namespace {
 
 constexpr int T256 = 256;
 
-__global__ __launch_bounds__(T256) void k_minmax_partial(const double* __restrict__ X, int64_t n,
-                                                         double* __restrict__ part,
-                                                         int* __restrict__ bad) {
-  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+// Monotone map of doubles to unsigned integers (exact min/max with atomics).
+__device__ __forceinline__ unsigned long long ord64(double d) {
+  unsigned long long u = (unsigned long long)__double_as_longlong(d);
+  return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double unord64(unsigned long long u) {
+  u = (u >> 63) ? (u & 0x7fffffffffffffffull) : ~u;
+  return __longlong_as_double((long long)u);
+}
+
+__device__ __forceinline__ int sys_of(const int64_t* __restrict__ off, int nsys, int64_t i) {
+  int a = 0, b = nsys - 1;   // largest s with off[s] <= i
+  while (a < b) {
+    int m = (a + b + 1) / 2;
+    if (off[m] <= i) a = m; else b = m - 1;
+  }
+  return a;
+}
+
+// Exact per-system bounding boxes: wave reduction when a wave's particles
+// belong to one system, ordered-integer atomics into mm[s][6].
+__global__ __launch_bounds__(T256) void k_minmax_sys(const double* __restrict__ X, int64_t n,
+                                                     const int64_t* __restrict__ off, int nsys,
+                                                     unsigned long long* __restrict__ mm,
+                                                     int* __restrict__ bad) {
+  int64_t i = (int64_t)blockIdx.x * T256 + threadIdx.x;
+  const bool act = i < n;
+  const int64_t ii = act ? i : n - 1;
+  const int s = sys_of(off, nsys, ii);
+  double v[3];
   bool nonfinite = false;
-  for (int64_t i = (int64_t)blockIdx.x * T256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * T256) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      double v = X[3 * i + d];
-      if (!isfinite(v)) nonfinite = true;
-      lo[d] = fmin(lo[d], v);
-      hi[d] = fmax(hi[d], v);
-    }
+  for (int d = 0; d < 3; ++d) {
+    v[d] = X[3 * ii + d];
+    if (act && !isfinite(v[d])) nonfinite = true;
   }
   if (nonfinite) atomicOr(bad, 1);
-  __shared__ double red[6][T256 / 64];
-  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    for (int o = 32; o > 0; o >>= 1) {
-      lo[d] = fmin(lo[d], __shfl_xor(lo[d], o, 64));
-      hi[d] = fmax(hi[d], __shfl_xor(hi[d], o, 64));
+  const int s0 = __shfl(s, 0, 64);
+  const bool uni = __all(s == s0);
+  if (uni) {
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = v[d];
+      hi[d] = v[d];
+      for (int o = 32; o > 0; o >>= 1) {
+        lo[d] = fmin(lo[d], __shfl_xor(lo[d], o, 64));
+        hi[d] = fmax(hi[d], __shfl_xor(hi[d], o, 64));
+      }
     }
-    if (lane == 0) { red[d][w] = lo[d]; red[3 + d][w] = hi[d]; }
-  }
-  __syncthreads();
-  if (threadIdx.x < 6) {
-    double v = red[threadIdx.x][0];
-    for (int i = 1; i < T256 / 64; ++i)
-      v = threadIdx.x < 3 ? fmin(v, red[threadIdx.x][i]) : fmax(v, red[threadIdx.x][i]);
-    part[6 * blockIdx.x + threadIdx.x] = v;
+    if ((threadIdx.x & 63) == 0)
+      for (int d = 0; d < 3; ++d) {
+        atomicMin(&mm[6 * s + d], ord64(lo[d]));
+        atomicMax(&mm[6 * s + 3 + d], ord64(hi[d]));
+      }
+  } else if (act) {
+    for (int d = 0; d < 3; ++d) {
+      atomicMin(&mm[6 * s + d], ord64(v[d]));
+      atomicMax(&mm[6 * s + 3 + d], ord64(v[d]));
+    }
   }
 }
 
-// Final reduction and the quantisation constants: lo[3], scale (2^(21-e)).
-__global__ void k_minmax_final(const double* __restrict__ part, int nb, double* __restrict__ q) {
-  if (threadIdx.x != 0) return;
-  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int b = 0; b < nb; ++b)
-    for (int d = 0; d < 3; ++d) {
-      lo[d] = fmin(lo[d], part[6 * b + d]);
-      hi[d] = fmax(hi[d], part[6 * b + 3 + d]);
-    }
+__global__ void k_mm_init(unsigned long long* __restrict__ mm, int nsys) {
+  int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < 6 * nsys) mm[i] = (i % 6) < 3 ? ~0ull : 0ull;
+}
+
+// Quantisation constants per system: lo[3], scale = 2^(21-e).
+__global__ void k_sys_final(const unsigned long long* __restrict__ mm, int nsys,
+                            double* __restrict__ q) {
+  int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= nsys) return;
+  double lo[3], hi[3];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = unord64(mm[6 * s + d]);
+    hi[d] = unord64(mm[6 * s + 3 + d]);
+  }
   double E = fmax(fmax(hi[0] - lo[0], hi[1] - lo[1]), hi[2] - lo[2]);
   int e = 0;
   if (E > 0.0) (void)frexp(E, &e);  // E = m 2^e, m in [0.5, 1): smallest e with 2^e > E
-  q[0] = lo[0]; q[1] = lo[1]; q[2] = lo[2];
-  q[3] = ldexp(1.0, 21 - e);
+  q[4 * s] = lo[0]; q[4 * s + 1] = lo[1]; q[4 * s + 2] = lo[2];
+  q[4 * s + 3] = ldexp(1.0, 21 - e);
 }
 
 __device__ __forceinline__ uint64_t spread3(uint64_t v) {
@@ -81,24 +114,52 @@ __device__ __forceinline__ uint64_t spread3(uint64_t v) {
   return v;
 }
 
+__device__ __forceinline__ uint64_t morton_of(const double* __restrict__ x,
+                                              const double* __restrict__ q) {
+  const double cap = 2097151.0;
+  double fx = fmin(floor((x[0] - q[0]) * q[3]), cap);
+  double fy = fmin(floor((x[1] - q[1]) * q[3]), cap);
+  double fz = fmin(floor((x[2] - q[2]) * q[3]), cap);
+  return (spread3((uint64_t)fx) << 2) | (spread3((uint64_t)fy) << 1) | spread3((uint64_t)fz);
+}
+
 __global__ __launch_bounds__(T256) void k_morton(const double* __restrict__ X, int64_t n,
+                                                 const int64_t* __restrict__ off, int nsys,
                                                  const double* __restrict__ q,
                                                  uint64_t* __restrict__ keys,
                                                  uint32_t* __restrict__ idx) {
   int64_t i = (int64_t)blockIdx.x * T256 + threadIdx.x;
   if (i >= n) return;
-  const double lo0 = q[0], lo1 = q[1], lo2 = q[2], sc = q[3];
-  const double cap = 2097151.0;
-  double fx = fmin(floor((X[3 * i] - lo0) * sc), cap);
-  double fy = fmin(floor((X[3 * i + 1] - lo1) * sc), cap);
-  double fz = fmin(floor((X[3 * i + 2] - lo2) * sc), cap);
-  uint64_t k = (spread3((uint64_t)fx) << 2) | (spread3((uint64_t)fy) << 1) | spread3((uint64_t)fz);
-  keys[i] = k;
+  keys[i] = morton_of(X + 3 * i, q + 4 * sys_of(off, nsys, i));
   idx[i] = (uint32_t)i;
+}
+
+// Second key of the segmented sort: the system of each (key-sorted) particle.
+__global__ __launch_bounds__(T256) void k_syskey(const uint32_t* __restrict__ idx, int64_t n,
+                                                 const int64_t* __restrict__ off, int nsys,
+                                                 uint64_t* __restrict__ k2) {
+  int64_t p = (int64_t)blockIdx.x * T256 + threadIdx.x;
+  if (p < n) k2[p] = (uint64_t)sys_of(off, nsys, idx[p]);
+}
+
+// Final order: Morton keys and systems at each sorted position.
+__global__ __launch_bounds__(T256) void k_rekey(const double* __restrict__ X, int64_t n,
+                                                const int64_t* __restrict__ off, int nsys,
+                                                const double* __restrict__ q,
+                                                const uint32_t* __restrict__ idx,
+                                                uint64_t* __restrict__ keys,
+                                                int32_t* __restrict__ sysk) {
+  int64_t p = (int64_t)blockIdx.x * T256 + threadIdx.x;
+  if (p >= n) return;
+  const int64_t i = idx[p];
+  const int s = sys_of(off, nsys, i);
+  keys[p] = morton_of(X + 3 * i, q + 4 * s);
+  sysk[p] = s;
 }
 
 __global__ __launch_bounds__(T256) void k_gather_check(const double* __restrict__ X, int64_t n,
                                                        const uint64_t* __restrict__ keys,
+                                                       const int32_t* __restrict__ sysk,
                                                        const uint32_t* __restrict__ idx,
                                                        double* __restrict__ xs,
                                                        int32_t* __restrict__ perm,
@@ -109,9 +170,11 @@ __global__ __launch_bounds__(T256) void k_gather_check(const double* __restrict_
   double x0 = X[3 * (int64_t)o], x1 = X[3 * (int64_t)o + 1], x2 = X[3 * (int64_t)o + 2];
   xs[3 * s] = x0; xs[3 * s + 1] = x1; xs[3 * s + 2] = x2;
   perm[s] = (int32_t)o;
-  // identical positions have identical keys: compare within the run of equal keys
+  // identical positions of one system have identical keys: compare within
+  // the run of equal (system, key)
   uint64_t k = keys[s];
-  for (int64_t t = s + 1; t < n && keys[t] == k; ++t) {
+  int32_t sy = sysk[s];
+  for (int64_t t = s + 1; t < n && keys[t] == k && sysk[t] == sy; ++t) {
     if (t - s > 4096) { atomicOr(dup, 2); break; }
     uint32_t u = idx[t];
     if (X[3 * (int64_t)u] == x0 && X[3 * (int64_t)u + 1] == x1 && X[3 * (int64_t)u + 2] == x2) {
@@ -121,37 +184,44 @@ __global__ __launch_bounds__(T256) void k_gather_check(const double* __restrict_
   }
 }
 
-// Common-prefix length of sorted keys at positions i, j (index tie-break).
-__device__ __forceinline__ int delta(const uint64_t* __restrict__ k, int64_t n, int64_t i,
-                                     int64_t j) {
+// Common-prefix length of the sorted (system, key, position) strings at
+// positions i, j: sbits system bits, then 64 key bits, then 32 position bits.
+__device__ __forceinline__ int delta(const uint64_t* __restrict__ k, const int32_t* __restrict__ sy,
+                                     int sbits, int64_t n, int64_t i, int64_t j) {
   if (j < 0 || j >= n) return -1;
-  uint64_t a = k[i], b = k[j];
-  if (a != b) return __clzll((long long)(a ^ b));
-  return 64 + __clz((int)((uint32_t)i ^ (uint32_t)j));
+  if (sbits > 0) {
+    int a = sy[i], b = sy[j];
+    if (a != b) return __clz(a ^ b) - (32 - sbits);
+  }
+  uint64_t ka = k[i], kb = k[j];
+  if (ka != kb) return sbits + __clzll((long long)(ka ^ kb));
+  return sbits + 64 + __clz((int)((uint32_t)i ^ (uint32_t)j));
 }
 
 // Binary radix tree (one thread per internal node i in [0, n-2]).
 // rng[i] = (first, last) inclusive; kid[i] = (left, right) in the combined id
 // space: internal node u -> u, sorted position s -> (n-1) + s.
-__global__ __launch_bounds__(T256) void k_radix_tree(const uint64_t* __restrict__ k, int64_t n,
-                                                     int2* __restrict__ rng, int2* __restrict__ kid,
+__global__ __launch_bounds__(T256) void k_radix_tree(const uint64_t* __restrict__ k,
+                                                     const int32_t* __restrict__ sy, int sbits,
+                                                     int64_t n, int2* __restrict__ rng,
+                                                     int2* __restrict__ kid,
                                                      int32_t* __restrict__ par) {
   int64_t i = (int64_t)blockIdx.x * T256 + threadIdx.x;
   if (i >= n - 1) return;
-  int d = (delta(k, n, i, i + 1) - delta(k, n, i, i - 1)) >= 0 ? 1 : -1;
-  int dmin = delta(k, n, i, i - d);
+  int d = (delta(k, sy, sbits, n, i, i + 1) - delta(k, sy, sbits, n, i, i - 1)) >= 0 ? 1 : -1;
+  int dmin = delta(k, sy, sbits, n, i, i - d);
   int64_t lmax = 2;
-  while (delta(k, n, i, i + lmax * d) > dmin) lmax *= 2;
+  while (delta(k, sy, sbits, n, i, i + lmax * d) > dmin) lmax *= 2;
   int64_t l = 0;
   for (int64_t t = lmax / 2; t >= 1; t /= 2)
-    if (delta(k, n, i, i + (l + t) * d) > dmin) l += t;
+    if (delta(k, sy, sbits, n, i, i + (l + t) * d) > dmin) l += t;
   int64_t j = i + l * d;
-  int dnode = delta(k, n, i, j);
+  int dnode = delta(k, sy, sbits, n, i, j);
   int64_t s = 0;
   int64_t t = l;
   do {
     t = (t + 1) / 2;
-    if (delta(k, n, i, i + (s + t) * d) > dnode) s += t;
+    if (delta(k, sy, sbits, n, i, i + (s + t) * d) > dnode) s += t;
   } while (t > 1);
   int64_t g = i + s * d + (d < 0 ? -1 : 0);
   int64_t first = i < j ? i : j, last = i < j ? j : i;
@@ -167,23 +237,36 @@ __device__ __forceinline__ int2 node_range(const int2* __restrict__ rng, int64_t
   return u < n - 1 ? rng[u] : make_int2(u - (int)(n - 1), u - (int)(n - 1));
 }
 
+// A node spans several systems when its first and last particle differ in
+// system; such nodes only join system roots and are not part of the tree.
+__device__ __forceinline__ bool mixed(const int2* __restrict__ rng, const int32_t* __restrict__ sy,
+                                      int64_t n, int u) {
+  int2 r = node_range(rng, n, u);
+  return sy[r.x] != sy[r.y];
+}
+
 __device__ __forceinline__ bool splittable(const int2* __restrict__ rng,
-                                           const uint64_t* __restrict__ k, int64_t n, int u,
+                                           const uint64_t* __restrict__ k,
+                                           const int32_t* __restrict__ sy, int64_t n, int u,
                                            int c_leaf) {
   if (u >= n - 1) return false;
   int2 r = rng[u];
-  return (r.y - r.x + 1) >= c_leaf && k[r.x] != k[r.y];
+  return sy[r.x] == sy[r.y] && (r.y - r.x + 1) >= c_leaf && k[r.x] != k[r.y];
 }
 
+// kept: a system root (no parent, or a parent spanning systems) or a son of
+// a splittable node.
 __global__ __launch_bounds__(T256) void k_keep(const int2* __restrict__ rng,
                                                const int32_t* __restrict__ par,
-                                               const uint64_t* __restrict__ k, int64_t n,
+                                               const uint64_t* __restrict__ k,
+                                               const int32_t* __restrict__ sy, int64_t n,
                                                int c_leaf, int64_t* __restrict__ flag) {
   int64_t u = (int64_t)blockIdx.x * T256 + threadIdx.x;
   if (u >= 2 * n - 1) return;
-  int root = n > 1 ? 0 : 0;
-  bool kept = (u == root) || (par[u] >= 0 && splittable(rng, k, n, par[u], c_leaf));
-  if (n == 1) kept = (u == 0);
+  bool kept;
+  if (mixed(rng, sy, n, (int)u)) kept = false;
+  else if (par[u] < 0 || mixed(rng, sy, n, par[u])) kept = true;
+  else kept = splittable(rng, k, sy, n, par[u], c_leaf);
   flag[u] = kept ? 1 : 0;
 }
 
@@ -209,7 +292,8 @@ __global__ __launch_bounds__(T256) void k_map(const uint32_t* __restrict__ sval,
 __global__ __launch_bounds__(T256) void k_nodes(const uint32_t* __restrict__ sval, int64_t m,
                                                 const int2* __restrict__ rng,
                                                 const int2* __restrict__ kid,
-                                                const uint64_t* __restrict__ k, int64_t n,
+                                                const uint64_t* __restrict__ k,
+                                                const int32_t* __restrict__ sy, int64_t n,
                                                 int c_leaf, const int32_t* __restrict__ map,
                                                 int4* __restrict__ nodes,
                                                 int32_t* __restrict__ parent,
@@ -219,14 +303,13 @@ __global__ __launch_bounds__(T256) void k_nodes(const uint32_t* __restrict__ sva
   int u = (int)sval[p];
   int2 r = node_range(rng, n, u);
   int4 nd = make_int4(r.x, r.y + 1, -1, -1);
-  if (splittable(rng, k, n, u, c_leaf)) {
+  if (splittable(rng, k, sy, n, u, c_leaf)) {
     int2 c = kid[u];
     nd.z = map[c.x];
     nd.w = map[c.y];
     parent[nd.z] = (int)p;
     parent[nd.w] = (int)p;
   }
-  if (p == 0) parent[0] = -1;
   nodes[p] = nd;
   isleaf[p] = nd.z < 0 ? 1 : 0;
 }
@@ -320,9 +403,138 @@ __global__ __launch_bounds__(T256) void k_inner_box(const int4* __restrict__ nod
     }
 }
 
+// System roots: kept nodes without a parent, indexed by the system of their
+// first particle.
+__global__ __launch_bounds__(T256) void k_roots(const int4* __restrict__ nodes, int64_t m,
+                                                const int32_t* __restrict__ parent,
+                                                const int32_t* __restrict__ sysk,
+                                                int32_t* __restrict__ roots) {
+  int64_t p = (int64_t)blockIdx.x * T256 + threadIdx.x;
+  if (p < m && parent[p] < 0) roots[sysk[nodes[p].x]] = (int32_t)p;
+}
+
 inline unsigned nblk(int64_t n, int t = T256) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
+
+static void build_tree_impl(hh_ctx ctx, hh_tree_s* t, const double* X, int64_t n,
+                            const std::vector<int64_t>& offs, int32_t c_leaf) {
+  hipStream_t st = ctx->stream;
+  const int nsys = (int)offs.size() - 1;
+  int sbits = 0;
+  while ((1 << sbits) < nsys) ++sbits;
+  t->ctx = ctx;
+  t->n = n;
+  t->c_leaf = c_leaf;
+  t->n_sys = nsys;
+  t->offs_host = offs;
+  t->offs.alloc(st, (nsys + 1) * sizeof(int64_t));
+  HIP_OK(hipMemcpyAsync(t->offs.p, offs.data(), (nsys + 1) * sizeof(int64_t),
+                        hipMemcpyHostToDevice, st));
+  const int64_t* off = t->offs.as<int64_t>();
+  // a1: per-system box, quantisation constants, Morton keys
+  DevBuf mm, qc;
+  mm.alloc(st, 6 * nsys * sizeof(unsigned long long));
+  qc.alloc(st, 4 * nsys * sizeof(double));
+  int* flags = (int*)ctx->scratch_flag.p;   // [0] non-finite, [1] duplicates
+  HIP_OK(hipMemsetAsync(flags, 0, 4 * sizeof(int), st));
+  hipLaunchKernelGGL(k_mm_init, dim3((6 * nsys + 255) / 256), dim3(256), 0, st,
+                     mm.as<unsigned long long>(), nsys);
+  hipLaunchKernelGGL(k_minmax_sys, dim3(nblk(n)), dim3(T256), 0, st, X, n, off, nsys,
+                     mm.as<unsigned long long>(), flags);
+  hipLaunchKernelGGL(k_sys_final, dim3((nsys + 255) / 256), dim3(256), 0, st,
+                     mm.as<unsigned long long>(), nsys, qc.as<double>());
+  t->keys.alloc(st, n * sizeof(uint64_t));
+  DevBuf idx, sysk;
+  idx.alloc(st, n * sizeof(uint32_t));
+  sysk.alloc(st, n * sizeof(int32_t));
+  hipLaunchKernelGGL(k_morton, dim3(nblk(n)), dim3(T256), 0, st, X, n, off, nsys,
+                     qc.as<double>(), t->keys.as<uint64_t>(), idx.as<uint32_t>());
+  HIP_OK(hipGetLastError());
+  // a2: stable sort by key, then (several systems) stably by system
+  radix_sort_u64(ctx, t->keys.as<uint64_t>(), idx.as<uint32_t>(), n, 63);
+  if (nsys > 1) {
+    hipLaunchKernelGGL(k_syskey, dim3(nblk(n)), dim3(T256), 0, st, idx.as<uint32_t>(), n, off,
+                       nsys, t->keys.as<uint64_t>());
+    radix_sort_u64(ctx, t->keys.as<uint64_t>(), idx.as<uint32_t>(), n, sbits);
+  }
+  hipLaunchKernelGGL(k_rekey, dim3(nblk(n)), dim3(T256), 0, st, X, n, off, nsys,
+                     qc.as<double>(), idx.as<uint32_t>(), t->keys.as<uint64_t>(),
+                     sysk.as<int32_t>());
+  t->xs.alloc(st, 3 * n * sizeof(double));
+  t->perm.alloc(st, n * sizeof(int32_t));
+  hipLaunchKernelGGL(k_gather_check, dim3(nblk(n)), dim3(T256), 0, st, X, n,
+                     t->keys.as<uint64_t>(), sysk.as<int32_t>(), idx.as<uint32_t>(),
+                     t->xs.as<double>(), t->perm.as<int32_t>(), flags + 1);
+  HIP_OK(hipGetLastError());
+  // a3: radix tree, truncation, pre-order
+  int64_t nt = 2 * n - 1;
+  DevBuf rng, kid, par, keep, kpos;
+  rng.alloc(st, std::max<int64_t>(1, n - 1) * sizeof(int2));
+  kid.alloc(st, std::max<int64_t>(1, n - 1) * sizeof(int2));
+  par.alloc(st, nt * sizeof(int32_t));
+  HIP_OK(hipMemsetAsync(par.p, 0xff, nt * sizeof(int32_t), st));
+  if (n > 1)
+    hipLaunchKernelGGL(k_radix_tree, dim3(nblk(n - 1)), dim3(T256), 0, st,
+                       t->keys.as<uint64_t>(), sysk.as<int32_t>(), sbits, n, rng.as<int2>(),
+                       kid.as<int2>(), par.as<int32_t>());
+  keep.alloc(st, (nt + 1) * sizeof(int64_t));
+  kpos.alloc(st, (nt + 1) * sizeof(int64_t));
+  HIP_OK(hipMemsetAsync(keep.as<int64_t>() + nt, 0, sizeof(int64_t), st));
+  hipLaunchKernelGGL(k_keep, dim3(nblk(nt)), dim3(T256), 0, st, rng.as<int2>(),
+                     par.as<int32_t>(), t->keys.as<uint64_t>(), sysk.as<int32_t>(), n, c_leaf,
+                     keep.as<int64_t>());
+  scan_exclusive_i64(ctx, keep.as<int64_t>(), kpos.as<int64_t>(), nt + 1);
+  HIP_OK(hipMemcpyAsync(ctx->pinned, kpos.as<int64_t>() + nt, 8, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(ctx->pinned + 1, flags, 8, hipMemcpyDeviceToHost, st));
+  ctx_sync(ctx);
+  int64_t m = ctx->pinned[0];
+  int fl_nonfinite = ((int*)(ctx->pinned + 1))[0], fl_dup = ((int*)(ctx->pinned + 1))[1];
+  HH_REQUIRE(!fl_nonfinite, HH_ERR_INVALID_ARG, "X holds a non-finite coordinate");
+  HH_REQUIRE(!fl_dup, HH_ERR_DUPLICATE_POINTS, "two particles have identical positions");
+  t->n_nodes = m;
+  DevBuf skey, sval, map;
+  skey.alloc(st, m * sizeof(uint64_t));
+  sval.alloc(st, m * sizeof(uint32_t));
+  hipLaunchKernelGGL(k_keep_emit, dim3(nblk(nt)), dim3(T256), 0, st, rng.as<int2>(),
+                     keep.as<int64_t>(), kpos.as<int64_t>(), n, skey.as<uint64_t>(),
+                     sval.as<uint32_t>());
+  int bits = 32;
+  while ((1ll << (bits - 32)) <= n) ++bits;
+  radix_sort_u64(ctx, skey.as<uint64_t>(), sval.as<uint32_t>(), m, bits);
+  map.alloc(st, nt * sizeof(int32_t));
+  hipLaunchKernelGGL(k_map, dim3(nblk(m)), dim3(T256), 0, st, sval.as<uint32_t>(), m,
+                     map.as<int32_t>());
+  t->nodes.alloc(st, m * sizeof(int4));
+  t->parent.alloc(st, m * sizeof(int32_t));
+  HIP_OK(hipMemsetAsync(t->parent.p, 0xff, m * sizeof(int32_t), st));
+  DevBuf isleaf, lpos;
+  isleaf.alloc(st, (m + 1) * sizeof(int64_t));
+  lpos.alloc(st, (m + 1) * sizeof(int64_t));
+  HIP_OK(hipMemsetAsync(isleaf.as<int64_t>() + m, 0, sizeof(int64_t), st));
+  hipLaunchKernelGGL(k_nodes, dim3(nblk(m)), dim3(T256), 0, st, sval.as<uint32_t>(), m,
+                     rng.as<int2>(), kid.as<int2>(), t->keys.as<uint64_t>(), sysk.as<int32_t>(),
+                     n, c_leaf, map.as<int32_t>(), t->nodes.as<int4>(), t->parent.as<int32_t>(),
+                     isleaf.as<int64_t>());
+  t->roots.alloc(st, nsys * sizeof(int32_t));
+  hipLaunchKernelGGL(k_roots, dim3(nblk(m)), dim3(T256), 0, st, t->nodes.as<int4>(), m,
+                     t->parent.as<int32_t>(), sysk.as<int32_t>(), t->roots.as<int32_t>());
+  scan_exclusive_i64(ctx, isleaf.as<int64_t>(), lpos.as<int64_t>(), m + 1);
+  int64_t nl = read_i64(ctx, lpos.as<int64_t>() + m);
+  t->n_leaves = nl;
+  t->leaf_id.alloc(st, m * sizeof(int32_t));
+  t->leaves.alloc(st, nl * sizeof(int32_t));
+  hipLaunchKernelGGL(k_leaves, dim3(nblk(m)), dim3(T256), 0, st, isleaf.as<int64_t>(),
+                     lpos.as<int64_t>(), m, t->leaf_id.as<int32_t>(), t->leaves.as<int32_t>());
+  t->leaf_of.alloc(st, n * sizeof(int32_t));
+  t->bbox.alloc(st, 6 * m * sizeof(double));
+  hipLaunchKernelGGL(k_leaf_box, dim3(nblk(nl * 64)), dim3(T256), 0, st,
+                     t->leaves.as<int32_t>(), nl, t->nodes.as<int4>(), t->xs.as<double>(),
+                     t->leaf_of.as<int32_t>(), t->bbox.as<double>());
+  hipLaunchKernelGGL(k_inner_box, dim3(nblk(m * 64)), dim3(T256), 0, st, t->nodes.as<int4>(), m,
+                     t->leaves.as<int32_t>(), nl, t->bbox.as<double>());
+  HIP_OK(hipGetLastError());
+}
 
 extern "C" {
 
@@ -332,100 +544,35 @@ hh_status hh_build_tree(hh_ctx ctx, const double* X, int64_t n, int32_t c_leaf, 
   HH_REQUIRE(out && X, HH_ERR_INVALID_ARG, "NULL argument");
   HH_REQUIRE(n >= 1 && n < (1ll << 31) - 1, HH_ERR_INVALID_ARG, "n must be in [1, 2^31-2]");
   HH_REQUIRE(c_leaf >= 2, HH_ERR_INVALID_ARG, "c_leaf must be >= 2");
-  hipStream_t st = ctx->stream;
   PhaseTimer timer(ctx, HH_PHASE_TREE);
   hh_tree_s* t = new hh_tree_s();
   try {
-    t->ctx = ctx;
-    t->n = n;
-    t->c_leaf = c_leaf;
-    // a1: box, quantisation constants, Morton keys
-    int nbmm = (int)std::min<int64_t>(1024, nblk(n));
-    DevBuf part, qc, keys_tmp;
-    part.alloc(st, 6 * nbmm * sizeof(double));
-    qc.alloc(st, 4 * sizeof(double));
-    int* flags = (int*)ctx->scratch_flag.p;   // [0] non-finite, [1] duplicates
-    HIP_OK(hipMemsetAsync(flags, 0, 4 * sizeof(int), st));
-    hipLaunchKernelGGL(k_minmax_partial, dim3(nbmm), dim3(T256), 0, st, X, n,
-                       part.as<double>(), flags);
-    hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(64), 0, st, part.as<double>(), nbmm,
-                       qc.as<double>());
-    t->keys.alloc(st, n * sizeof(uint64_t));
-    DevBuf idx;
-    idx.alloc(st, n * sizeof(uint32_t));
-    hipLaunchKernelGGL(k_morton, dim3(nblk(n)), dim3(T256), 0, st, X, n, qc.as<double>(),
-                       t->keys.as<uint64_t>(), idx.as<uint32_t>());
-    HIP_OK(hipGetLastError());
-    // a2: stable sort by key (ties keep input order), gather, duplicate check
-    radix_sort_u64(ctx, t->keys.as<uint64_t>(), idx.as<uint32_t>(), n, 63);
-    t->xs.alloc(st, 3 * n * sizeof(double));
-    t->perm.alloc(st, n * sizeof(int32_t));
-    hipLaunchKernelGGL(k_gather_check, dim3(nblk(n)), dim3(T256), 0, st, X, n,
-                       t->keys.as<uint64_t>(), idx.as<uint32_t>(), t->xs.as<double>(),
-                       t->perm.as<int32_t>(), flags + 1);
-    HIP_OK(hipGetLastError());
-    // a3: radix tree, truncation, pre-order
-    int64_t nt = 2 * n - 1;
-    DevBuf rng, kid, par, keep, kpos;
-    rng.alloc(st, std::max<int64_t>(1, n - 1) * sizeof(int2));
-    kid.alloc(st, std::max<int64_t>(1, n - 1) * sizeof(int2));
-    par.alloc(st, nt * sizeof(int32_t));
-    HIP_OK(hipMemsetAsync(par.p, 0xff, nt * sizeof(int32_t), st));
-    if (n > 1)
-      hipLaunchKernelGGL(k_radix_tree, dim3(nblk(n - 1)), dim3(T256), 0, st,
-                         t->keys.as<uint64_t>(), n, rng.as<int2>(), kid.as<int2>(),
-                         par.as<int32_t>());
-    keep.alloc(st, (nt + 1) * sizeof(int64_t));
-    kpos.alloc(st, (nt + 1) * sizeof(int64_t));
-    HIP_OK(hipMemsetAsync(keep.as<int64_t>() + nt, 0, sizeof(int64_t), st));
-    hipLaunchKernelGGL(k_keep, dim3(nblk(nt)), dim3(T256), 0, st, rng.as<int2>(),
-                       par.as<int32_t>(), t->keys.as<uint64_t>(), n, c_leaf, keep.as<int64_t>());
-    scan_exclusive_i64(ctx, keep.as<int64_t>(), kpos.as<int64_t>(), nt + 1);
-    HIP_OK(hipMemcpyAsync(ctx->pinned, kpos.as<int64_t>() + nt, 8, hipMemcpyDeviceToHost, st));
-    HIP_OK(hipMemcpyAsync(ctx->pinned + 1, flags, 8, hipMemcpyDeviceToHost, st));
-    ctx_sync(ctx);
-    int64_t m = ctx->pinned[0];
-    int fl_nonfinite = ((int*)(ctx->pinned + 1))[0], fl_dup = ((int*)(ctx->pinned + 1))[1];
-    HH_REQUIRE(!fl_nonfinite, HH_ERR_INVALID_ARG, "X holds a non-finite coordinate");
-    HH_REQUIRE(!fl_dup, HH_ERR_DUPLICATE_POINTS, "two particles have identical positions");
-    t->n_nodes = m;
-    DevBuf skey, sval, map;
-    skey.alloc(st, m * sizeof(uint64_t));
-    sval.alloc(st, m * sizeof(uint32_t));
-    hipLaunchKernelGGL(k_keep_emit, dim3(nblk(nt)), dim3(T256), 0, st, rng.as<int2>(),
-                       keep.as<int64_t>(), kpos.as<int64_t>(), n, skey.as<uint64_t>(),
-                       sval.as<uint32_t>());
-    int bits = 32;
-    while ((1ll << (bits - 32)) <= n) ++bits;
-    radix_sort_u64(ctx, skey.as<uint64_t>(), sval.as<uint32_t>(), m, bits);
-    map.alloc(st, nt * sizeof(int32_t));
-    hipLaunchKernelGGL(k_map, dim3(nblk(m)), dim3(T256), 0, st, sval.as<uint32_t>(), m,
-                       map.as<int32_t>());
-    t->nodes.alloc(st, m * sizeof(int4));
-    t->parent.alloc(st, m * sizeof(int32_t));
-    DevBuf isleaf, lpos;
-    isleaf.alloc(st, (m + 1) * sizeof(int64_t));
-    lpos.alloc(st, (m + 1) * sizeof(int64_t));
-    HIP_OK(hipMemsetAsync(isleaf.as<int64_t>() + m, 0, sizeof(int64_t), st));
-    hipLaunchKernelGGL(k_nodes, dim3(nblk(m)), dim3(T256), 0, st, sval.as<uint32_t>(), m,
-                       rng.as<int2>(), kid.as<int2>(), t->keys.as<uint64_t>(), n, c_leaf,
-                       map.as<int32_t>(), t->nodes.as<int4>(), t->parent.as<int32_t>(),
-                       isleaf.as<int64_t>());
-    scan_exclusive_i64(ctx, isleaf.as<int64_t>(), lpos.as<int64_t>(), m + 1);
-    int64_t nl = read_i64(ctx, lpos.as<int64_t>() + m);
-    t->n_leaves = nl;
-    t->leaf_id.alloc(st, m * sizeof(int32_t));
-    t->leaves.alloc(st, nl * sizeof(int32_t));
-    hipLaunchKernelGGL(k_leaves, dim3(nblk(m)), dim3(T256), 0, st, isleaf.as<int64_t>(),
-                       lpos.as<int64_t>(), m, t->leaf_id.as<int32_t>(), t->leaves.as<int32_t>());
-    t->leaf_of.alloc(st, n * sizeof(int32_t));
-    t->bbox.alloc(st, 6 * m * sizeof(double));
-    hipLaunchKernelGGL(k_leaf_box, dim3(nblk(nl * 64)), dim3(T256), 0, st,
-                       t->leaves.as<int32_t>(), nl, t->nodes.as<int4>(), t->xs.as<double>(),
-                       t->leaf_of.as<int32_t>(), t->bbox.as<double>());
-    hipLaunchKernelGGL(k_inner_box, dim3(nblk(m * 64)), dim3(T256), 0, st, t->nodes.as<int4>(), m,
-                       t->leaves.as<int32_t>(), nl, t->bbox.as<double>());
-    HIP_OK(hipGetLastError());
+    build_tree_impl(ctx, t, X, n, std::vector<int64_t>{0, n}, c_leaf);
+  } catch (...) {
+    delete t;
+    throw;
+  }
+  *out = t;
+  HH_API_END(ctx)
+}
+
+hh_status hh_build_tree_batch(hh_ctx ctx, const double* X, const int64_t* offsets, int32_t n_sys,
+                              int32_t c_leaf, hh_tree* out) {
+  if (out) *out = nullptr;
+  HH_API_BEGIN(ctx)
+  HH_REQUIRE(out && X && offsets, HH_ERR_INVALID_ARG, "NULL argument");
+  HH_REQUIRE(n_sys >= 1 && n_sys <= (1 << 20), HH_ERR_INVALID_ARG, "n_sys must be in [1, 2^20]");
+  HH_REQUIRE(c_leaf >= 2, HH_ERR_INVALID_ARG, "c_leaf must be >= 2");
+  std::vector<int64_t> offs(offsets, offsets + n_sys + 1);
+  HH_REQUIRE(offs[0] == 0, HH_ERR_INVALID_ARG, "offsets[0] must be 0");
+  for (int s = 0; s < n_sys; ++s)
+    HH_REQUIRE(offs[s + 1] > offs[s], HH_ERR_INVALID_ARG, "every system needs >= 1 particle");
+  const int64_t n = offs[n_sys];
+  HH_REQUIRE(n < (1ll << 31) - 1, HH_ERR_INVALID_ARG, "total n must be < 2^31-1");
+  PhaseTimer timer(ctx, HH_PHASE_TREE);
+  hh_tree_s* t = new hh_tree_s();
+  try {
+    build_tree_impl(ctx, t, X, n, offs, c_leaf);
   } catch (...) {
     delete t;
     throw;

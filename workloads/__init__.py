@@ -9,11 +9,13 @@ from .gen import (  # noqa: F401
     drop_radius,
     rsa_cube,
     lattice_sphere,
+    lattice_cube,
+    filament_chains,
+    batch_workload,
     normal_forces,
     gravity_forces,
     mlp_weights,
     sample_rows,
-    filament_system,
     batch_systems,
     workload,
     WORKLOADS,

@@ -180,6 +180,51 @@ def lattice_sphere(n: int, phi: float, jitter: float = 0.25, a: float = 1.0,
     return pts
 
 
+def lattice_cube(n: int, phi: float, jitter: float = 0.25, a: float = 1.0,
+                 seed: int = 0) -> np.ndarray:
+    """n points of a primitive cubic lattice filling a cube row by row (the
+    paper's perturbed-lattice construction, Sec. 4.1), jittered by U(+-j a) with
+    j = min(jitter, (s - 2.05 a) / (2 sqrt(3) a)) so centres stay >= 2.05 a apart."""
+    n = int(n)
+    s = a * (4.0 * math.pi / (3.0 * phi)) ** (1.0 / 3.0)
+    jitter = max(0.0, min(jitter, (s - 2.05 * a) / (2.0 * math.sqrt(3.0) * a)))
+    m = int(math.ceil(n ** (1.0 / 3.0)))
+    i = np.arange(n, dtype=np.int64)
+    pts = np.stack([i % m, (i // m) % m, i // (m * m)], axis=1).astype(np.float64) * s
+    rng = Rng(seed, "pos")
+    pts += rng.uniform_pm(3 * n, jitter * a).reshape(n, 3)
+    return pts
+
+
+def filament_chains(n: int, phi: float, beads: int = 50, bond: float = 2.2,
+                    bend_sd: float = 0.3, a: float = 1.0, seed: int = 0) -> np.ndarray:
+    """Chains of `beads` beads (n rounded down to a multiple of beads).
+
+    Chain starts are uniform in the cube sized for phi; each bond has length
+    `bond` and turns from the previous bond by a polar angle |theta|, theta ~
+    N(0, bend_sd), with uniform azimuth. Beads of different chains are not
+    kept apart (no overlap resolution across chains).
+    """
+    nchain = max(1, int(n) // beads)
+    L = cube_side(nchain * beads, phi, a)
+    rng = Rng(seed, "chain")
+    pos = np.empty((nchain, beads, 3))
+    pos[:, 0] = rng.uniform(3 * nchain).reshape(nchain, 3) * L
+    d = rng.normal(3 * nchain).reshape(nchain, 3)
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    for b in range(1, beads):
+        th = np.abs(rng.normal(nchain)) * bend_sd
+        ps = rng.uniform(nchain) * 2.0 * math.pi
+        hp = np.where(np.abs(d[:, :1]) < 0.9, [[1.0, 0.0, 0.0]], [[0.0, 1.0, 0.0]])
+        u = np.cross(d, hp)
+        u /= np.linalg.norm(u, axis=1)[:, None]
+        v = np.cross(d, u)
+        d = (np.cos(th)[:, None] * d + np.sin(th)[:, None] *
+             (np.cos(ps)[:, None] * u + np.sin(ps)[:, None] * v))
+        pos[:, b] = pos[:, b - 1] + bond * a * d
+    return pos.reshape(-1, 3)
+
+
 def normal_forces(n: int, seed: int = 0, scale: float = 1.0,
                   dtype=np.float64) -> np.ndarray:
     """F_i ~ N(0, scale^2 I3)."""
@@ -215,82 +260,6 @@ def sample_rows(n: int, k: int, seed: int = 3) -> np.ndarray:
     return np.sort(pick).astype(np.int64)
 
 
-def _rotate_bond(prev: np.ndarray, theta: float, psi: float) -> np.ndarray:
-    """Unit vector at polar angle theta from prev, azimuth psi around it."""
-    t = prev / np.linalg.norm(prev)
-    helper = np.array([1.0, 0.0, 0.0]) if abs(t[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
-    u = np.cross(t, helper)
-    u /= np.linalg.norm(u)
-    v = np.cross(t, u)
-    return math.cos(theta) * t + math.sin(theta) * (math.cos(psi) * u + math.sin(psi) * v)
-
-
-def filament_system(n: int, phi: float, beads: int = 50, bond: float = 2.2,
-                    bend_sd: float = 0.3, min_dist: float = 2.05, a: float = 1.0,
-                    seed: int = 0, max_tries: int = 100) -> np.ndarray:
-    """Chains of `beads` beads (n rounded down to a multiple of beads).
-
-    Each chain starts at a uniform point of the cube sized for phi; each bond has
-    length `bond` and turns from the previous bond by a polar angle |theta|,
-    theta ~ N(0, bend_sd), with uniform azimuth. A bead closer than min_dist to
-    any earlier non-adjacent bead is redrawn (up to max_tries times).
-    """
-    nchain = int(n) // beads
-    n = nchain * beads
-    L = cube_side(n, phi, a)
-    rng = Rng(seed, "chain")
-    pos = np.empty((n, 3))
-    nc = max(1, int(math.floor(L / min_dist)))
-    w = L / nc
-    cells: dict = {}
-    d2min = min_dist * min_dist
-
-    def clash(p, skip):
-        c = np.floor(p / w).astype(np.int64)
-        for dx in (-1, 0, 1):
-            for dy in (-1, 0, 1):
-                for dz in (-1, 0, 1):
-                    lst = cells.get((int(c[0] + dx), int(c[1] + dy), int(c[2] + dz)))
-                    if not lst:
-                        continue
-                    for q in lst:
-                        if q == skip:
-                            continue
-                        d = pos[q] - p
-                        if d @ d < d2min:
-                            return True
-        return False
-
-    def add(idx, p):
-        c = np.floor(p / w).astype(np.int64)
-        cells.setdefault((int(c[0]), int(c[1]), int(c[2])), []).append(idx)
-
-    k = 0
-    for _ in range(nchain):
-        for attempt in range(10 * max_tries):
-            p = rng.uniform(3) * L
-            if not clash(p, -1):
-                break
-        pos[k] = p
-        add(k, p)
-        k += 1
-        d = rng.normal(3)
-        d /= np.linalg.norm(d)
-        for _b in range(1, beads):
-            for attempt in range(max_tries):
-                th = abs(float(rng.normal(1)[0])) * bend_sd
-                ps = float(rng.uniform(1)[0]) * 2.0 * math.pi
-                nd = _rotate_bond(d, th, ps)
-                p = pos[k - 1] + bond * a * nd
-                if not clash(p, k - 1):
-                    break
-            d = nd
-            pos[k] = p
-            add(k, p)
-            k += 1
-    return pos
-
-
 def batch_systems(n_sys: int = 64, nmin: int = 5000, nmax: int = 200000, seed: int = 2):
     """Per-system sizes (log-uniform in [nmin, nmax]), kinds and volume fractions.
 
@@ -310,6 +279,23 @@ def batch_systems(n_sys: int = 64, nmin: int = 5000, nmax: int = 200000, seed: i
             n = max(50, (n // 50) * 50)
         out.append({"n": n, "kind": kind, "phi": float(phis[s]), "seed": 1000 + s})
     return out
+
+
+def batch_workload(n_sys: int = 64, nmin: int = 5000, nmax: int = 200000, seed: int = 2):
+    """Positions, forces and offsets of the batched workload: even systems are
+    free spheres (perturbed lattice in a cube at phi ~ U[0.05, 0.30]), odd ones
+    flexible filaments (50-bead chains, bond 2.2 a, bending N(0, 0.3))."""
+    specs = batch_systems(n_sys, nmin, nmax, seed)
+    Xs, Fs, off = [], [], [0]
+    for sp in specs:
+        if sp["kind"] == "spheres":
+            X = lattice_cube(sp["n"], sp["phi"], seed=sp["seed"])
+        else:
+            X = filament_chains(sp["n"], sp["phi"], seed=sp["seed"])
+        Xs.append(X)
+        Fs.append(normal_forces(X.shape[0], seed=sp["seed"]))
+        off.append(off[-1] + X.shape[0])
+    return np.concatenate(Xs), np.concatenate(Fs), np.asarray(off, dtype=np.int64), specs
 
 
 # Named workloads (positions generator, forces, kernel, H-matrix parameters).
