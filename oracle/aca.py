@@ -8,7 +8,7 @@ c_k is right-multiplied by the inverse of its pivot entry; q_k^T is the
 residual row i_k; the next column pivot j_{k+1} maximises the magnitude of
 q_k over columns not yet used (Eq. (9)). With nu = ||c_k q_k^T||_F and
 lambda = ||C Q||_F the iteration stops when nu <= zeta lambda (Eq. (10)),
-lambda^2 being updated incrementally (Algorithm 2, line 10).
+lambda^2 being updated incrementally (Algorithm 2).
 
 Readings where the paper is silent or inconsistent (listed in the design notes):
   * entry magnitude for pivoting: the squared Frobenius norm of the 3x3 entry
@@ -83,11 +83,11 @@ def aca_entries(col, row, c: int, q: int, eps: float, l_max: int,
     converged = False
     for k in range(kmax):
         used_j[j] = True
-        # line 4: residual column j_k
+        # residual column j_k
         a = np.array(col(j), dtype=np.float64)             # [c, 3, 3]
         for m in range(k):
             a = a - Cs[m] @ Qs[m][j]
-        # line 5: row pivot
+        # row pivot
         nrm = np.sum(a * a, axis=(1, 2))
         if np.max(np.where(used_i, -1.0, nrm)) <= TINY * lam2:
             converged = True
@@ -97,18 +97,18 @@ def aca_entries(col, row, c: int, q: int, eps: float, l_max: int,
         fro = np.sqrt(np.sum(P * P))
         if abs(np.linalg.det(P)) <= SING * fro ** 3:
             break
-        # line 6: normalise by the pivot entry
+        # normalise by the pivot entry
         ck = a @ np.linalg.inv(P)
-        # line 7: residual row i_k
+        # residual row i_k
         b = np.array(row(ik), dtype=np.float64)            # [q, 3, 3]
         for m in range(k):
             b = b - Cs[m][ik] @ Qs[m]
         qk = b
         used_i[ik] = True
-        # line 8: next column pivot
+        # next column pivot
         nq = np.where(used_j, -1.0, _magnitude(qk, pivot))
         jn = int(np.argmax(nq))
-        # lines 9-10: nu^2 and lambda^2 via 3x3 Gram matrices
+        # nu^2 and lambda^2 via 3x3 Gram matrices
         Akk = np.einsum("iab,iac->bc", ck, ck)
         Bkk = np.einsum("jab,jcb->ac", qk, qk)
         nu2 = float(np.trace(Akk @ Bkk))
@@ -118,14 +118,14 @@ def aca_entries(col, row, c: int, q: int, eps: float, l_max: int,
             Bkm = np.einsum("jab,jcb->ac", qk, Qs[m])     # sum_j q_k(j) q_m(j)^T
             cross += float(np.trace(Amk @ Bkm))
         lam2 = lam2 + nu2 + 2.0 * cross
-        # line 11: append
+        # append the term
         Cs.append(ck)
         Qs.append(qk)
         I.append(ik)
         J.append(j)
         nus.append(nu2)
         lams.append(lam2)
-        # line 12: stopping test
+        # stopping test
         if nu2 <= eps * eps * lam2:
             converged = True
             break

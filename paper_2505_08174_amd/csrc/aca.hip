@@ -3,14 +3,14 @@
 // One workgroup (256 threads) per admissible block, fetched from a global
 // work counter (dynamic load balance; the results do not depend on the
 // order). The rank loop runs inside the workgroup:
-//   column j_k: a(i) = K(x_i - y_j) - sum_{m<k} c_m(i) q_m(j)          (line 4)
-//   i_k = argmax over unused rows of ||a(i)||_F^2, lowest index on ties (line 5)
-//   c_k(i) = a(i) P^-1, P = a(i_k)                                     (line 6)
-//   row i_k:  q_k(j) = K(x_ik - y_j) - sum_{m<k} c_m(i_k) q_m(j)       (line 7)
-//   j_{k+1} = argmax over unused columns of ||q_k(j)||_F^2             (line 8)
-//   nu^2 = tr(A_kk B_kk), lambda^2 += nu^2 + 2 sum_{m<k} tr(A_mk B_km)  (lines 9-10)
+//   column j_k: a(i) = K(x_i - y_j) - sum_{m<k} c_m(i) q_m(j)
+//   i_k = argmax over unused rows of ||a(i)||_F^2, lowest index on ties
+//   c_k(i) = a(i) P^-1, P = a(i_k)
+//   row i_k:  q_k(j) = K(x_ik - y_j) - sum_{m<k} c_m(i_k) q_m(j)
+//   j_{k+1} = argmax over unused columns of ||q_k(j)||_F^2
+//   nu^2 = tr(A_kk B_kk), lambda^2 += nu^2 + 2 sum_{m<k} tr(A_mk B_km)
 //   with A_mk = sum_i c_m(i)^T c_k(i), B_km = sum_j q_k(j) q_m(j)^T
-//   stop when nu^2 <= eps^2 lambda^2 (line 12) or min(c, q) terms.
+//   stop when nu^2 <= eps^2 lambda^2 or after min(c, q) terms.
 // Pivot magnitude: squared Frobenius norm in the FP64 form (Algorithm 2);
 // |det| of the 3x3 entry in the FP32 and BF16 forms (the magnitude the text
 // around Eq. (9) names), which avoids nearly singular pivots whose inverse
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(ACA_T) void k_aca(AcaArgs<T> a) {
       __syncthreads();
       T* Ck = a.pool + s_off[k];
       T* Qk = Ck + 9 * (int64_t)c;
-      // line 4-5: residual column j and its largest unused entry
+      // residual column j and its largest unused entry
       NT best = -1, bestf = -1;   // selection magnitude, largest squared norm
       int bi = 0x7fffffff;
       NT graw = 0;   // largest raw entry of the column (precision floor)
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(ACA_T) void k_aca(AcaArgs<T> a) {
       }
       __syncthreads();
       if (s_stop) { fallback = true; break; }
-      // line 6: c_k = a P^-1
+      // normalisation: c_k = a P^-1
       for (int i = tid; i < c; i += ACA_T) {
         T v[9], o[9];
         for (int e = 0; e < 9; ++e) v[e] = Ck[9 * (int64_t)i + e];
@@ -282,7 +282,7 @@ __global__ __launch_bounds__(ACA_T) void k_aca(AcaArgs<T> a) {
         s_ci[t] = a.pool[s_off[m] + 9 * (int64_t)ik + e];
       }
       __syncthreads();
-      // lines 7-8: residual row i_k and the next column pivot
+      // residual row i_k and the next column pivot
       const double xi0 = xt[3 * ik], xi1 = xt[3 * ik + 1], xi2 = xt[3 * ik + 2];
       best = -1;
       bi = 0x7fffffff;
@@ -358,7 +358,7 @@ __global__ __launch_bounds__(ACA_T) void k_aca(AcaArgs<T> a) {
           ub[3 * i + 2] += (double)e[6] * t0 + (double)e[7] * t1 + (double)e[8] * t2;
         }
       }
-      // lines 9-10: Gram matrices, nu^2 and the lambda^2 update
+      // Gram matrices, nu^2 and the lambda^2 update
       __syncthreads();   // all of c_k and q_k are written
       NT nu2 = 0, cross = 0;
       for (int m0 = 0; m0 <= k; m0 += GCH) {

@@ -6,7 +6,7 @@
 //  dF = alpha_1 w + (near field with the displacement reversed) + Q^T (C^T w)
 //  dX, dtheta: every near pair (i, j) re-evaluates the MLP and back-propagates
 //  the cotangent w_i F_j^T (no pair activations are stored); every admissible
-//  block runs the reverse of the ACA recursion (Algorithm 2 lines 4-7 with
+//  block runs the reverse of the ACA recursion (the column, pivot and row steps of Algorithm 2, with
 //  the pivots frozen; the pivot entry P_k equals q_k(j_k)), which yields a
 //  cotangent for every kernel sample it took, and those sampled pairs are
 //  back-propagated the same way.
