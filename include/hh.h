@@ -92,6 +92,11 @@ hh_status hh_ctx_set_stream(hh_ctx ctx, void* stream);
  * fit (a fixed buffer filled, applied and reused, Sec. 3.3.2). The default is
  * 40% of the free device memory at context creation. */
 hh_status hh_ctx_set_budget(hh_ctx ctx, size_t bytes);
+/* Work split of hh_aca_build / hh_matvec: admissible blocks with
+ * c + q >= team_min (rounded up to a power of two) are approximated by a
+ * whole workgroup of 8 waves, smaller ones by a single wave each (results
+ * agree to rounding). Default 4096; team_min in [64, 2^30]. */
+hh_status hh_ctx_set_team_min(hh_ctx ctx, int32_t team_min);
 /* Wait for all work enqueued by this context. */
 hh_status hh_synchronize(hh_ctx ctx);
 

@@ -31,6 +31,7 @@ SIGNATURES = {
     "hh_ctx_set_stream": (C.c_int, [_vp, _vp]),
     "hh_synchronize": (C.c_int, [_vp]),
     "hh_ctx_set_budget": (C.c_int, [_vp, C.c_size_t]),
+    "hh_ctx_set_team_min": (C.c_int, [_vp, C.c_int32]),
     "hh_kernel_create_rpy": (C.c_int, [_vp, _d, _d, C.POINTER(_vp)]),
     "hh_kernel_create_mlp": (C.c_int, [_vp, _pd, C.c_int, _d, _d, C.POINTER(_vp)]),
     "hh_kernel_free": (None, [_vp]),

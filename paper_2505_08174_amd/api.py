@@ -48,6 +48,10 @@ class Context:
     def set_budget(self, nbytes: int):
         self.check(L.load().hh_ctx_set_budget(self.h, int(nbytes)))
 
+    def set_team_min(self, team_min: int):
+        """Blocks with c + q >= team_min go to whole workgroups (default 4096)."""
+        self.check(L.load().hh_ctx_set_team_min(self.h, int(team_min)))
+
     def set_profiling(self, on: bool):
         self.check(L.load().hh_ctx_set_profiling(self.h, int(bool(on))))
 

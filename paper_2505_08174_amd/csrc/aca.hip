@@ -1,13 +1,13 @@
 // Adaptive cross approximation with 3x3 entries (Algorithm 2, Eqs. (8)-(10)).
 //
-// One workgroup (256 threads) per admissible block, fetched from a global
-// work counter (dynamic load balance; the results do not depend on the
-// order). The rank loop runs inside the workgroup:
+// One wave (64 lanes) per admissible block, fetched from a global work
+// counter (dynamic load balance; the results do not depend on the order).
+// The rank loop runs inside the wave:
 //   column j_k: a(i) = K(x_i - y_j) - sum_{m<k} c_m(i) q_m(j)
-//   i_k = argmax over unused rows of ||a(i)||_F^2, lowest index on ties
+//   i_k = argmax over unused rows of the pivot magnitude, lowest index on ties
 //   c_k(i) = a(i) P^-1, P = a(i_k)
 //   row i_k:  q_k(j) = K(x_ik - y_j) - sum_{m<k} c_m(i_k) q_m(j)
-//   j_{k+1} = argmax over unused columns of ||q_k(j)||_F^2
+//   j_{k+1} = argmax over unused columns of the pivot magnitude of q_k(j)
 //   nu^2 = tr(A_kk B_kk), lambda^2 += nu^2 + 2 sum_{m<k} tr(A_mk B_km)
 //   with A_mk = sum_i c_m(i)^T c_k(i), B_km = sum_j q_k(j) q_m(j)^T
 //   stop when nu^2 <= eps^2 lambda^2 or after min(c, q) terms.
@@ -20,22 +20,25 @@
 // l_max terms without convergence end with a dense fallback.
 // Factors c_k (c entries) and q_k (q entries), 9 values each, are stored
 // contiguously per step in a pool; each step bump-allocates 9 (c + q) values.
-// Row and column samples are evaluated with the VALU kernel, in the working
-// type T; norms, pivots and Gram sums in NT.
+// Samples, residuals and factors are in the working type T; pivots, norms
+// and Gram matrices in FP64 in every form. In the BF16 form the samples come
+// from the MFMA MLP tile (activations carried as BF16 hi + lo).
 #include "devmath.h"
 #include "internal.h"
 #include "mlp_mfma.h"
 
 namespace {
 
-constexpr int ACA_T = 256;
-constexpr int NW = ACA_T / 64;
-constexpr int GCH = 8;   // Gram matrices reduced per LDS round
+constexpr int AW = 8;              // block workers (waves) per workgroup
+constexpr int AW_T = 64 * AW;
+constexpr int RCH = 2;             // rows per lane per chunk
+constexpr int CH = 64 * RCH;       // rows per chunk
 
 template <class T>
 struct AcaArgs {
   const int2* G;
   int64_t nG;
+  const int32_t* order;   // blocks of each launch range, largest first
   const int4* nodes;
   const double* xs;
   KParams kp;
@@ -49,7 +52,9 @@ struct AcaArgs {
   int64_t pool_elems;
   unsigned long long* pool_top;
   int* overflow;
-  int* work;         // dynamic block counter
+  int* work;         // dynamic block counter (blocks worked on by single waves)
+  int* work_big;     // dynamic block counter (blocks worked on by whole workgroups)
+  int64_t nbig;      // order[b0 .. b0 + nbig) go to whole workgroups
   int64_t b0, b1;    // block range of this launch
   // fused apply (streamed mode): Fs != nullptr
   const T* Fs;       // sorted forces
@@ -57,6 +62,9 @@ struct AcaArgs {
   const int64_t* uoff;
   const uint4* frags;   // BF16 MFMA weight fragments (MF kernels)
   int det_pivot;        // pivot magnitude |det| (else squared Frobenius norm)
+  double* gram;         // Gram history A, B (gram_half doubles each) and cross-wave
+  int64_t gram_stride;  // partials, gram_stride doubles per worker
+  int64_t gram_half;
 };
 
 template <class NT, class T>
@@ -82,349 +90,599 @@ __device__ __forceinline__ void mfma_entry(const bf16x8* fr, int mode, double dx
   K[6] = K[2];            K[7] = K[5];              K[8] = 2.0f * o[8] * s;
 }
 
-// block-wide argmax (ties to the lowest index), result broadcast to all threads
-template <class NT>
-__device__ __forceinline__ void block_argmax(NT& v, int& i, NT* sv, int* si) {
-  wave_argmax(v, i);
-  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) { sv[w] = v; si[w] = i; }
-  __syncthreads();
-  v = sv[0];
-  i = si[0];
-  for (int k = 1; k < NW; ++k)
-    if (sv[k] > v || (sv[k] == v && si[k] < i)) { v = sv[k]; i = si[k]; }
+__device__ __forceinline__ int tri(int m) { return m * (m + 1) / 2; }
+
+// Orders the wave's earlier global and LDS writes before its later reads by
+// other lanes (all lanes of one wave share the CU's L1 and LDS).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
 }
 
-template <class T, class NT, int KIND, bool MF>
-__global__ __launch_bounds__(ACA_T) void k_aca(AcaArgs<T> a) {
-  // MF: kernel samples from the BF16 MFMA MLP (weights as LDS fragments)
-  __shared__ T wl[(KIND == KIND_MLP && !MF) ? MLP_NP : 1];
-  __shared__ bf16x8 fr[MF ? FR_TOTAL : 1];
-  __shared__ T s_qj[LMAX_CAP * 9];   // q_m(j_k), m < k
-  __shared__ T s_ci[LMAX_CAP * 9];   // c_m(i_k), m < k
-  __shared__ T s_pinv[9];
-  __shared__ int64_t s_off[LMAX_CAP];
-  __shared__ int s_pi[LMAX_CAP], s_pj[LMAX_CAP + 1];
-  __shared__ NT s_red[NW][GCH][18];
-  __shared__ NT s_av[NW];
-  __shared__ int s_ai[NW];
-  __shared__ NT s_lam2;
-  __shared__ double s_t[NW][3];
-  __shared__ int s_b, s_stop, s_fb;
-  if (MF) {
-    stage_frags(fr, a.frags, ACA_T);
-  } else if (KIND == KIND_MLP) {
-    const T* w = (const T*)a.kp.w;
-    for (int i = threadIdx.x; i < MLP_NP; i += ACA_T) wl[i] = w[i];
+template <int N>
+__device__ __forceinline__ void wave_sumv(double (&p)[N]) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int e = 0; e < N; ++e) p[e] += __shfl_xor(p[e], o, 64);
+}
+
+template <class T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    T w = __shfl_xor(v, o, 64);
+    v = w > v ? w : v;
   }
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  return v;
+}
+
+// K -= A B (3x3, row-major)
+template <class T>
+__device__ __forceinline__ void sub_mm(T K[9], const T A[9], const T B[9]) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+      K[3 * r + cc] -= A[3 * r] * B[cc] + A[3 * r + 1] * B[3 + cc] + A[3 * r + 2] * B[6 + cc];
+}
+
+__device__ __forceinline__ void mul_mm(const double A[9], const double B[9], double O[9]) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+      O[3 * r + cc] = A[3 * r] * B[cc] + A[3 * r + 1] * B[3 + cc] + A[3 * r + 2] * B[6 + cc];
+}
+
+// 3x3 history matrix of the Gram store, transposed when lo > hi
+__device__ __forceinline__ void load_hist(const double* __restrict__ h, int m1, int m2,
+                                          double M[9]) {
+  if (m1 <= m2) {
+    const double* s = h + 9 * (tri(m2) + m1);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) M[e] = s[e];
+  } else {
+    const double* s = h + 9 * (tri(m1) + m2);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) M[3 * r + cc] = s[3 * cc + r];
+  }
+}
+
+// Scratch of one worker team (TW waves) for the block it approximates.
+template <class T>
+struct TeamSh {
+  T qc[LMAX_CAP * 9];     // q_m(j_k) in the column pass, c_m(i_k) in the row pass
+  int64_t off[LMAX_CAP];  // pool offset of factor m
+  int pi[LMAX_CAP];
+  int pj[LMAX_CAP + 1];
+  int64_t bo;             // broadcast: claimed block, pool offset
+  int ovf;                // broadcast: pool overflow
+};
+
+// Cross-wave partial results of a team of AW waves (one per workgroup).
+struct TeamRed {
+  double v[AW][16];
+  int i[AW];
+};
+
+template <int TW>
+__device__ __forceinline__ void team_sync() {
+  if constexpr (TW == 1)
+    wave_sync();
+  else
+    __syncthreads();
+}
+
+// Raw samples K(sgn (p_i - y)) for rows i in [0, n) of `pts`, written to
+// slot[9 i ..]: 32-row MFMA tiles, lanes l and l + 32 share a row, the tiles
+// spread over the TW waves of the team.
+template <int TW>
+__device__ __forceinline__ void sample_mfma(const bf16x8* fr, int mode, const double* pts, int n,
+                                            double y0, double y1, double y2, double sgn,
+                                            float* slot, int wit) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll 1
+  for (int t0 = 32 * wit; t0 < n; t0 += 32 * TW) {
+    const int i = t0 + (lane & 31);
+    const int ii = i < n ? i : t0;
+    float K[9];
+    mfma_entry(fr, mode, sgn * (pts[3 * ii] - y0), sgn * (pts[3 * ii + 1] - y1),
+               sgn * (pts[3 * ii + 2] - y2), K);
+    if (i < n) {
+      if (lane < 32) {
+#pragma unroll
+        for (int e = 0; e < 5; ++e) slot[9 * (int64_t)i + e] = K[e];
+      } else {
+#pragma unroll
+        for (int e = 5; e < 9; ++e) slot[9 * (int64_t)i + e] = K[e];
+      }
+    }
+  }
+}
+
+// Combines the per-wave results of a pass over the team: sums v[0..NV) in
+// wave order, max of the two magnitudes, argmax (ties to the lowest index),
+// and sums the per-m partials (lane m of every wave) through global scratch.
+template <int TW, int NV>
+__device__ __forceinline__ void team_combine(TeamRed* tr, double* gx, int wit, int k,
+                                             double (&v)[NV], double& mx1, double& mx2,
+                                             double& best, int& bi, double (&G)[9]) {
+  if constexpr (TW > 1) {
+    const int lane = threadIdx.x & 63;
+    if (lane == 0) {
+#pragma unroll
+      for (int e = 0; e < NV; ++e) tr->v[wit][e] = v[e];
+      tr->v[wit][NV] = mx1;
+      tr->v[wit][NV + 1] = mx2;
+      tr->v[wit][NV + 2] = best;
+      tr->i[wit] = bi;
+    }
+    if (lane < k) {
+      double* d = gx + 9 * (64 * wit + lane);
+#pragma unroll
+      for (int e = 0; e < 9; ++e) d[e] = G[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+      double s = 0;
+      for (int w = 0; w < TW; ++w) s += tr->v[w][e];
+      v[e] = s;
+    }
+    mx1 = tr->v[0][NV];
+    mx2 = tr->v[0][NV + 1];
+    best = tr->v[0][NV + 2];
+    bi = tr->i[0];
+    for (int w = 1; w < TW; ++w) {
+      mx1 = tr->v[w][NV] > mx1 ? tr->v[w][NV] : mx1;
+      mx2 = tr->v[w][NV + 1] > mx2 ? tr->v[w][NV + 1] : mx2;
+      const double bw = tr->v[w][NV + 2];
+      const int iw = tr->i[w];
+      if (bw > best || (bw == best && iw < bi)) { best = bw; bi = iw; }
+    }
+    if (lane < k) {
+#pragma unroll
+      for (int e = 0; e < 9; ++e) G[e] = 0;
+      for (int w = 0; w < TW; ++w) {
+        const double* s = gx + 9 * (64 * w + lane);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) G[e] += s[e];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ACA of the blocks order[r0 .. r1) by teams of TW waves; `counter` hands out
+// the blocks. Per step k:
+//   column pass: raw column g(i) = K(x_i - y_j); residual
+//     a(i) = g(i) - sum_{m<k} c_m(i) q_m(j_k), subtracting term by term
+//     (partial residuals r_m = g - sum_{m'<m} ..., r_k = a); in the same pass
+//     Ghat_m = sum_i c_m(i)^T r_m(i) (one wave reduction per m and chunk);
+//   pivot i_k, c_k = a P^-1;
+//   A_mk = sum_i c_m(i)^T c_k(i) = (Ghat_m - sum_{m<=m'<k} A_mm' q_m'(j_k)) P^-1
+//     from the stored Gram history A_mm' (lane m works on m);
+//   row pass likewise: q_k(j) = h(j) - sum_m c_m(i_k) q_m(j),
+//     B_km = sum_j q_k(j) q_m(j)^T = Bhat_m - sum_{m<=m'<k} c_m'(i_k) B_m'm;
+//   nu^2 = tr(A_kk B_kk), lambda^2 += nu^2 + 2 sum_{m<k} tr(A_mk B_km).
+// So the Gram terms cost no extra pass over the factors. Every wave of a team
+// computes the per-step scalars itself from the same combined values, so all
+// decisions are uniform over the team. Fused apply: u(i) += c_{k-1}(i) t_{k-1}
+// rides on the next column pass (or a final pass).
+template <class T, int KIND, bool MF, int TW>
+__device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, const bf16x8* fr,
+                                           TeamSh<T>& sh, TeamRed* tr, int wit, int64_t slot,
+                                           int* counter, int64_t r0, int64_t r1) {
+  using NT = double;
+  const int lane = threadIdx.x & 63;
+  const bool lead = wit == 0 && lane == 0;
+  const int stride = 64 * TW;   // threads of the team
+  const int tid = 64 * wit + lane;
+  double* hA = a.gram + slot * a.gram_stride;
+  double* hB = hA + a.gram_half;
+  double* gx = hB + a.gram_half;   // cross-wave partials, [AW][64][9]
+#pragma unroll 1
   for (;;) {
-    __syncthreads();
-    if (tid == 0) s_b = atomicAdd(a.work, 1);
-    __syncthreads();
-    const int64_t b = a.b0 + s_b;
-    if (b >= a.b1) break;
-    const int2 g = a.G[b];
-    const int4 nt = a.nodes[g.x], ns = a.nodes[g.y];
+    if (lead) sh.bo = atomicAdd(counter, 1);
+    team_sync<TW>();
+    const int64_t sb = sh.bo;
+    if (r0 + sb >= r1) break;
+    const int64_t b = a.order[r0 + sb];
+    const int2 g2 = a.G[b];
+    const int4 nt = a.nodes[g2.x], ns = a.nodes[g2.y];
     const int c = nt.y - nt.x, q = ns.y - ns.x;
     const double* xt = a.xs + 3 * (int64_t)nt.x;
     const double* xsr = a.xs + 3 * (int64_t)ns.x;
     const int kmax = min(min(c, q), a.l_max);
     int j = q / 2;
     int rank = 0;
-    bool converged = false, fallback = false;
-    if (tid == 0) { s_lam2 = 0; s_stop = 0; s_fb = 0; }
+    bool converged = false, fallback = false, pending = false;
+    double lam2 = 0;
     const bool fuse = a.Fs != nullptr;
     double* ub = fuse ? a.ublk + 3 * (a.uoff[b] - a.uoff[a.b0]) : nullptr;
     if (fuse)
-      for (int i = tid; i < 3 * c; i += ACA_T) ub[i] = 0.0;
+#pragma unroll 1
+      for (int i = tid; i < 3 * c; i += stride) ub[i] = 0.0;
+    double tp0 = 0, tp1 = 0, tp2 = 0;   // t_{k-1} = sum_j q_{k-1}(j) F_j
+#pragma unroll 1
     for (int k = 0; k < kmax; ++k) {
-      __syncthreads();
-      if (tid == 0) {
-        s_pj[k] = j;
-        unsigned long long need = 9ull * (unsigned long long)(c + q);
-        unsigned long long off = atomicAdd(a.pool_top, need);
-        if ((int64_t)(off + need) > a.pool_elems) {
+      team_sync<TW>();   // sh.bo and sh.qc of the previous step are consumed
+      if (lead) {
+        const unsigned long long need = 9ull * (unsigned long long)(c + q);
+        const unsigned long long o = atomicAdd(a.pool_top, need);
+        int ovf = 0;
+        if ((int64_t)(o + need) > a.pool_elems) {
           atomicOr(a.overflow, 1);
-          s_fb = 1;
+          ovf = 1;
         }
-        s_off[k] = (int64_t)off;
-        a.fptr[b * LMAX_CAP + k] = (int64_t)off;
+        sh.bo = (int64_t)o;
+        sh.ovf = ovf;
+        sh.off[k] = (int64_t)o;
+        sh.pj[k] = j;
+        a.fptr[b * LMAX_CAP + k] = (int64_t)o;
       }
-      __syncthreads();
-      if (s_fb) { fallback = true; break; }
-      for (int t = tid; t < 9 * k; t += ACA_T) {
-        int m = t / 9, e = t % 9;
-        s_qj[t] = a.pool[s_off[m] + 9 * (int64_t)c + 9 * (int64_t)j + e];
+      team_sync<TW>();
+      if (sh.ovf) { fallback = true; break; }
+      const int64_t offv = sh.bo;
+#pragma unroll 1
+      for (int t = tid; t < 9 * k; t += stride) {
+        const int m = t / 9, e = t - 9 * m;
+        sh.qc[t] = a.pool[sh.off[m] + 9 * (int64_t)c + 9 * (int64_t)j + e];
       }
-      __syncthreads();
-      T* Ck = a.pool + s_off[k];
+      T* Ck = a.pool + offv;
       T* Qk = Ck + 9 * (int64_t)c;
-      // residual column j and its largest unused entry
-      NT best = -1, bestf = -1;   // selection magnitude, largest squared norm
-      int bi = 0x7fffffff;
-      NT graw = 0;   // largest raw entry of the column (precision floor)
       const double yj0 = xsr[3 * j], yj1 = xsr[3 * j + 1], yj2 = xsr[3 * j + 2];
-      if (MF) {
-        // raw column samples in 32-row MFMA tiles, parked in the c_k slot
-        for (int t0 = 32 * wv; t0 < c; t0 += 32 * NW) {
-          const int i = t0 + (lane & 31);
-          const int ii = i < c ? i : t0;
-          float K[9];
-          mfma_entry(fr, a.kp.input_mode, xt[3 * ii] - yj0, xt[3 * ii + 1] - yj1,
-                     xt[3 * ii + 2] - yj2, K);
-          if (i < c && lane < 32)
+      if (MF) sample_mfma<TW>(fr, a.kp.input_mode, xt, c, yj0, yj1, yj2, 1.0, (float*)Ck, wit);
+      team_sync<TW>();
+      // ---- column pass: residual, Ghat, pivot search, sum a^T a
+      NT best = -1, bestf = -1, graw = 0;
+      int bi = 0x7fffffff;
+      double G[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      double S[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 1
+      for (int base = CH * wit; base < c; base += CH * TW) {
+        T rs[RCH][9];
 #pragma unroll
-            for (int e = 0; e < 9; ++e) Ck[9 * (int64_t)i + e] = (T)K[e];
-        }
-        __syncthreads();
-      }
-      for (int i = tid; i < c; i += ACA_T) {
-        T K[9];
-        if (MF) {
+        for (int r = 0; r < RCH; ++r) {
+          const int i = base + 64 * r + lane;
+          if (i < c) {
+            if (MF) {
 #pragma unroll
-          for (int e = 0; e < 9; ++e) K[e] = Ck[9 * (int64_t)i + e];
-        } else {
-          kernel_entry<T>(a.kp, wl, (T)(xt[3 * i] - yj0), (T)(xt[3 * i + 1] - yj1),
-                          (T)(xt[3 * i + 2] - yj2), K);
-        }
-        if (sizeof(T) == 4) {
-          NT g2 = 0;
+              for (int e = 0; e < 9; ++e) rs[r][e] = Ck[9 * (int64_t)i + e];
+            } else {
+              kernel_entry<T>(a.kp, wl, (T)(xt[3 * i] - yj0), (T)(xt[3 * i + 1] - yj1),
+                              (T)(xt[3 * i + 2] - yj2), rs[r]);
+            }
+          } else {
 #pragma unroll
-          for (int e = 0; e < 9; ++e) g2 += (NT)K[e] * (NT)K[e];
-          graw = g2 > graw ? g2 : graw;
+            for (int e = 0; e < 9; ++e) rs[r][e] = 0;
+          }
+          if (sizeof(T) == 4) {
+            NT g2s = 0;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) g2s += (NT)rs[r][e] * (NT)rs[r][e];
+            graw = g2s > graw ? g2s : graw;
+          }
         }
+#pragma unroll 1
         for (int m = 0; m < k; ++m) {
-          const T* cm = a.pool + s_off[m] + 9 * (int64_t)i;
-          T cv[9];
+          const T* cm = a.pool + sh.off[m];
+          T qv[9];
 #pragma unroll
-          for (int e = 0; e < 9; ++e) cv[e] = cm[e];
-          const T* qm = s_qj + 9 * m;
+          for (int e = 0; e < 9; ++e) qv[e] = sh.qc[9 * m + e];
+          double p[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-          for (int r = 0; r < 3; ++r)
+          for (int r = 0; r < RCH; ++r) {
+            const int i = base + 64 * r + lane;
+            T cv[9];
 #pragma unroll
-            for (int cc = 0; cc < 3; ++cc)
-              K[3 * r + cc] -= cv[3 * r] * qm[cc] + cv[3 * r + 1] * qm[3 + cc] + cv[3 * r + 2] * qm[6 + cc];
+            for (int e = 0; e < 9; ++e) cv[e] = i < c ? cm[9 * (int64_t)i + e] : T(0);
+#pragma unroll
+            for (int x = 0; x < 3; ++x)
+#pragma unroll
+              for (int y = 0; y < 3; ++y)
+                p[3 * x + y] += (double)cv[x] * (double)rs[r][y] +
+                                (double)cv[3 + x] * (double)rs[r][3 + y] +
+                                (double)cv[6 + x] * (double)rs[r][6 + y];
+            sub_mm<T>(rs[r], cv, qv);
+            if (fuse && m == k - 1 && i < c) {
+              ub[3 * i] += (double)cv[0] * tp0 + (double)cv[1] * tp1 + (double)cv[2] * tp2;
+              ub[3 * i + 1] += (double)cv[3] * tp0 + (double)cv[4] * tp1 + (double)cv[5] * tp2;
+              ub[3 * i + 2] += (double)cv[6] * tp0 + (double)cv[7] * tp1 + (double)cv[8] * tp2;
+            }
+          }
+          wave_sumv(p);
+          if (lane == m) {
+#pragma unroll
+            for (int e = 0; e < 9; ++e) G[e] += p[e];
+          }
         }
-        NT nrm = 0;
 #pragma unroll
-        for (int e = 0; e < 9; ++e) {
-          Ck[9 * (int64_t)i + e] = K[e];
-          nrm += (NT)K[e] * (NT)K[e];
+        for (int r = 0; r < RCH; ++r) {
+          const int i = base + 64 * r + lane;
+          if (i >= c) continue;
+          NT nrm = 0;
+#pragma unroll
+          for (int e = 0; e < 9; ++e) {
+            Ck[9 * (int64_t)i + e] = rs[r][e];
+            nrm += (NT)rs[r][e] * (NT)rs[r][e];
+          }
+#pragma unroll
+          for (int x = 0; x < 3; ++x)
+#pragma unroll
+            for (int y = 0; y < 3; ++y)
+              S[3 * x + y] += (double)rs[r][x] * (double)rs[r][y] +
+                              (double)rs[r][3 + x] * (double)rs[r][3 + y] +
+                              (double)rs[r][6 + x] * (double)rs[r][6 + y];
+          NT sel = a.det_pivot ? det3<NT>(rs[r]) : nrm;
+          bool used = false;
+#pragma unroll 1
+          for (int m = 0; m < k; ++m) used |= (sh.pi[m] == i);
+          if (used) { nrm = -1; sel = -1; }
+          if (sel > best || (sel == best && i < bi)) { best = sel; bi = i; }
+          bestf = nrm > bestf ? nrm : bestf;
         }
-        NT sel = a.det_pivot ? det3<NT>(K) : nrm;
-        bool used = false;
-        for (int m = 0; m < k; ++m) used |= (s_pi[m] == i);
-        if (used) { nrm = -1; sel = -1; }
-        if (sel > best || (sel == best && i < bi)) { best = sel; bi = i; }
-        bestf = nrm > bestf ? nrm : bestf;
       }
-      if (sizeof(T) == 4) {
-        int dummy = 0;
-        block_argmax(graw, dummy, s_av, s_ai);
-      }
-      block_argmax(best, bi, s_av, s_ai);
-      if (a.det_pivot) {
-        int dummy = 0;
-        block_argmax(bestf, dummy, s_av, s_ai);
-      } else {
-        bestf = best;
-      }
+      pending = false;   // the term k-1 is applied
+      wave_sumv(S);
+      if (sizeof(T) == 4) graw = wave_max(graw);
+      wave_argmax(best, bi);
+      bestf = wave_max(bestf);
+      team_combine<TW>(tr, gx, wit, k, S, graw, bestf, best, bi, G);
+      if (!a.det_pivot) bestf = best;
       // no usable row (all used or non-finite): stop without a new term
       if (!(best >= NT(0)) || bi < 0 || bi >= c) { fallback = true; break; }
-      if (bestf <= NT(1e-30) * s_lam2) { converged = true; break; }
+      if (bestf <= NT(1e-30) * (NT)lam2) { converged = true; break; }
       // single precision: a residual at the rounding level of the raw column
       // (32 units of roundoff) carries no information; the block is converged
       if (sizeof(T) == 4 && bestf <= NT(3.6e-12) * graw) { converged = true; break; }
-      if (tid == 0) {
-        const T* P = Ck + 9 * (int64_t)bi;
-        double p[9];   // pivot determinant and inverse in FP64 in every form
-        for (int e = 0; e < 9; ++e) p[e] = (double)P[e];
-        double det = p[0] * (p[4] * p[8] - p[5] * p[7]) - p[1] * (p[3] * p[8] - p[5] * p[6]) +
-                     p[2] * (p[3] * p[7] - p[4] * p[6]);
-        double fro2 = 0;
-        for (int e = 0; e < 9; ++e) fro2 += p[e] * p[e];
-        double fro = sqrt(fro2);
-        if (!(fabs(det) > 1e-14 * fro2 * fro)) {
-          s_stop = 1;
-        } else {
-          double id = 1.0 / det;
-          s_pinv[0] = (T)((p[4] * p[8] - p[5] * p[7]) * id);
-          s_pinv[1] = (T)((p[2] * p[7] - p[1] * p[8]) * id);
-          s_pinv[2] = (T)((p[1] * p[5] - p[2] * p[4]) * id);
-          s_pinv[3] = (T)((p[5] * p[6] - p[3] * p[8]) * id);
-          s_pinv[4] = (T)((p[0] * p[8] - p[2] * p[6]) * id);
-          s_pinv[5] = (T)((p[2] * p[3] - p[0] * p[5]) * id);
-          s_pinv[6] = (T)((p[3] * p[7] - p[4] * p[6]) * id);
-          s_pinv[7] = (T)((p[1] * p[6] - p[0] * p[7]) * id);
-          s_pinv[8] = (T)((p[0] * p[4] - p[1] * p[3]) * id);
-        }
-        s_pi[k] = bi;
+      team_sync<TW>();
+      // pivot entry, determinant test and inverse in FP64 (every lane)
+      double P[9];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) P[e] = (double)Ck[9 * (int64_t)bi + e];
+      const double det = P[0] * (P[4] * P[8] - P[5] * P[7]) - P[1] * (P[3] * P[8] - P[5] * P[6]) +
+                         P[2] * (P[3] * P[7] - P[4] * P[6]);
+      double fro2 = 0;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) fro2 += P[e] * P[e];
+      if (!(fabs(det) > 1e-14 * fro2 * sqrt(fro2))) { fallback = true; break; }
+      const double id = 1.0 / det;
+      double Pi[9];
+      Pi[0] = (P[4] * P[8] - P[5] * P[7]) * id;
+      Pi[1] = (P[2] * P[7] - P[1] * P[8]) * id;
+      Pi[2] = (P[1] * P[5] - P[2] * P[4]) * id;
+      Pi[3] = (P[5] * P[6] - P[3] * P[8]) * id;
+      Pi[4] = (P[0] * P[8] - P[2] * P[6]) * id;
+      Pi[5] = (P[2] * P[3] - P[0] * P[5]) * id;
+      Pi[6] = (P[3] * P[7] - P[4] * P[6]) * id;
+      Pi[7] = (P[1] * P[6] - P[0] * P[7]) * id;
+      Pi[8] = (P[0] * P[4] - P[1] * P[3]) * id;
+      const int ik = bi;
+      if (lead) sh.pi[k] = ik;
+      // A_kk = Pi^T S Pi; A_mk = (Ghat_m - sum_m' A_mm' q_m'(j)) Pi (lane m)
+      double Akk[9];
+      {
+        double SP[9], PiT[9];
+        mul_mm(S, Pi, SP);
+#pragma unroll
+        for (int x = 0; x < 3; ++x)
+#pragma unroll
+          for (int y = 0; y < 3; ++y) PiT[3 * x + y] = Pi[3 * y + x];
+        mul_mm(PiT, SP, Akk);
       }
-      __syncthreads();
-      if (s_stop) { fallback = true; break; }
+      if (lane < k) {
+#pragma unroll 1
+        for (int m2 = lane; m2 < k; ++m2) {
+          double Am[9], qd[9];
+          load_hist(hA, lane, m2, Am);
+#pragma unroll
+          for (int e = 0; e < 9; ++e) qd[e] = (double)sh.qc[9 * m2 + e];
+          sub_mm<double>(G, Am, qd);
+        }
+        double Amk[9];
+        mul_mm(G, Pi, Amk);
+        if (wit == 0) {
+          double* d = hA + 9 * (tri(k) + lane);
+#pragma unroll
+          for (int e = 0; e < 9; ++e) d[e] = Amk[e];
+        }
+      }
+      if (lead) {
+        double* d = hA + 9 * (tri(k) + k);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) d[e] = Akk[e];
+      }
       // normalisation: c_k = a P^-1
-      for (int i = tid; i < c; i += ACA_T) {
+      T pt[9];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) pt[e] = (T)Pi[e];
+#pragma unroll 1
+      for (int i = tid; i < c; i += stride) {
         T v[9], o[9];
+#pragma unroll
         for (int e = 0; e < 9; ++e) v[e] = Ck[9 * (int64_t)i + e];
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
           for (int cc = 0; cc < 3; ++cc)
-            o[3 * r + cc] = v[3 * r] * s_pinv[cc] + v[3 * r + 1] * s_pinv[3 + cc] + v[3 * r + 2] * s_pinv[6 + cc];
+            o[3 * r + cc] = v[3 * r] * pt[cc] + v[3 * r + 1] * pt[3 + cc] + v[3 * r + 2] * pt[6 + cc];
+#pragma unroll
         for (int e = 0; e < 9; ++e) Ck[9 * (int64_t)i + e] = o[e];
       }
-      __syncthreads();
-      const int ik = s_pi[k];
-      for (int t = tid; t < 9 * k; t += ACA_T) {
-        int m = t / 9, e = t % 9;
-        s_ci[t] = a.pool[s_off[m] + 9 * (int64_t)ik + e];
+      team_sync<TW>();   // A side done with sh.qc; c_k written
+#pragma unroll 1
+      for (int t = tid; t < 9 * k; t += stride) {
+        const int m = t / 9, e = t - 9 * m;
+        sh.qc[t] = a.pool[sh.off[m] + 9 * (int64_t)ik + e];
       }
-      __syncthreads();
-      // residual row i_k and the next column pivot
       const double xi0 = xt[3 * ik], xi1 = xt[3 * ik + 1], xi2 = xt[3 * ik + 2];
+      if (MF) sample_mfma<TW>(fr, a.kp.input_mode, xsr, q, xi0, xi1, xi2, -1.0, (float*)Qk, wit);
+      team_sync<TW>();
+      // ---- row pass: residual, Bhat, next column pivot, sum q_k q_k^T, t_k
       best = -1;
       bi = 0x7fffffff;
-      double tp0 = 0, tp1 = 0, tp2 = 0;   // t_k = sum_j q_k(j) F_j (fused apply)
-      if (MF) {
-        for (int t0 = 32 * wv; t0 < q; t0 += 32 * NW) {
-          const int jj = t0 + (lane & 31);
-          const int jc = jj < q ? jj : t0;
-          float K[9];
-          mfma_entry(fr, a.kp.input_mode, xi0 - xsr[3 * jc], xi1 - xsr[3 * jc + 1],
-                     xi2 - xsr[3 * jc + 2], K);
-          if (jj < q && lane < 32)
+      double SB[12];   // B_kk (9), then t_k (3)
 #pragma unroll
-            for (int e = 0; e < 9; ++e) Qk[9 * (int64_t)jj + e] = (T)K[e];
-        }
-        __syncthreads();
-      }
-      for (int jj = tid; jj < q; jj += ACA_T) {
-        T K[9];
-        if (MF) {
+      for (int e = 0; e < 12; ++e) SB[e] = 0;
 #pragma unroll
-          for (int e = 0; e < 9; ++e) K[e] = Qk[9 * (int64_t)jj + e];
-        } else {
-          kernel_entry<T>(a.kp, wl, (T)(xi0 - xsr[3 * jj]), (T)(xi1 - xsr[3 * jj + 1]),
-                          (T)(xi2 - xsr[3 * jj + 2]), K);
-        }
-        for (int m = 0; m < k; ++m) {
-          const T* qm = a.pool + s_off[m] + 9 * (int64_t)c + 9 * (int64_t)jj;
-          T qv[9];
+      for (int e = 0; e < 9; ++e) G[e] = 0;   // now Bhat_m
+#pragma unroll 1
+      for (int base = CH * wit; base < q; base += CH * TW) {
+        T rs[RCH][9];
 #pragma unroll
-          for (int e = 0; e < 9; ++e) qv[e] = qm[e];
-          const T* cm = s_ci + 9 * m;
+        for (int r = 0; r < RCH; ++r) {
+          const int jj = base + 64 * r + lane;
+          if (jj < q) {
+            if (MF) {
 #pragma unroll
-          for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int cc = 0; cc < 3; ++cc)
-              K[3 * r + cc] -= cm[3 * r] * qv[cc] + cm[3 * r + 1] * qv[3 + cc] + cm[3 * r + 2] * qv[6 + cc];
-        }
-        NT nrm = 0;
-#pragma unroll
-        for (int e = 0; e < 9; ++e) {
-          Qk[9 * (int64_t)jj + e] = K[e];
-          nrm += (NT)K[e] * (NT)K[e];
-        }
-        if (fuse) {
-          const T* f = a.Fs + 3 * ((int64_t)ns.x + jj);
-          const double f0 = f[0], f1 = f[1], f2 = f[2];
-          tp0 += (double)K[0] * f0 + (double)K[1] * f1 + (double)K[2] * f2;
-          tp1 += (double)K[3] * f0 + (double)K[4] * f1 + (double)K[5] * f2;
-          tp2 += (double)K[6] * f0 + (double)K[7] * f1 + (double)K[8] * f2;
-        }
-        NT sel = a.det_pivot ? det3<NT>(K) : nrm;
-        bool used = false;
-        for (int m = 0; m <= k; ++m) used |= (s_pj[m] == jj);
-        if (used) sel = -1;
-        if (sel > best || (sel == best && jj < bi)) { best = sel; bi = jj; }
-      }
-      block_argmax(best, bi, s_av, s_ai);
-      const int jn = (bi >= 0 && bi < q) ? bi : -1;   // -1 only when every column is used
-      if (fuse) {
-        // u_i += c_k(i) t_k for the rows of this block (owner thread per row)
-        tp0 = wave_sum(tp0);
-        tp1 = wave_sum(tp1);
-        tp2 = wave_sum(tp2);
-        if (lane == 0) { s_t[wv][0] = tp0; s_t[wv][1] = tp1; s_t[wv][2] = tp2; }
-        __syncthreads();
-        double t0 = 0, t1 = 0, t2 = 0;
-        for (int w = 0; w < NW; ++w) { t0 += s_t[w][0]; t1 += s_t[w][1]; t2 += s_t[w][2]; }
-        for (int i = tid; i < c; i += ACA_T) {
-          const T* e = Ck + 9 * (int64_t)i;
-          ub[3 * i] += (double)e[0] * t0 + (double)e[1] * t1 + (double)e[2] * t2;
-          ub[3 * i + 1] += (double)e[3] * t0 + (double)e[4] * t1 + (double)e[5] * t2;
-          ub[3 * i + 2] += (double)e[6] * t0 + (double)e[7] * t1 + (double)e[8] * t2;
-        }
-      }
-      // Gram matrices, nu^2 and the lambda^2 update
-      __syncthreads();   // all of c_k and q_k are written
-      NT nu2 = 0, cross = 0;
-      for (int m0 = 0; m0 <= k; m0 += GCH) {
-        const int mc = min(GCH, k + 1 - m0);
-        for (int mm = 0; mm < mc; ++mm) {
-          const int m = m0 + mm;
-          NT A[9] = {0}, B[9] = {0};
-          const T* Cm = a.pool + s_off[m];
-          const T* Qm = Cm + 9 * (int64_t)c;
-          for (int i = tid; i < c; i += ACA_T) {
-            T x[9], y[9];
-            for (int e = 0; e < 9; ++e) { x[e] = Cm[9 * (int64_t)i + e]; y[e] = Ck[9 * (int64_t)i + e]; }
-            for (int r = 0; r < 3; ++r)
-              for (int cc = 0; cc < 3; ++cc)
-                A[3 * r + cc] += (NT)x[r] * (NT)y[cc] + (NT)x[3 + r] * (NT)y[3 + cc] + (NT)x[6 + r] * (NT)y[6 + cc];
-          }
-          for (int jj = tid; jj < q; jj += ACA_T) {
-            T x[9], y[9];
-            for (int e = 0; e < 9; ++e) { x[e] = Qk[9 * (int64_t)jj + e]; y[e] = Qm[9 * (int64_t)jj + e]; }
-            for (int r = 0; r < 3; ++r)
-              for (int cc = 0; cc < 3; ++cc)
-                B[3 * r + cc] += (NT)x[3 * r] * (NT)y[3 * cc] + (NT)x[3 * r + 1] * (NT)y[3 * cc + 1] + (NT)x[3 * r + 2] * (NT)y[3 * cc + 2];
-          }
-          for (int e = 0; e < 9; ++e) {
-            NT sa = wave_sum(A[e]), sb = wave_sum(B[e]);
-            if (lane == 0) { s_red[wv][mm][e] = sa; s_red[wv][mm][9 + e] = sb; }
-          }
-        }
-        __syncthreads();
-        if (tid == 0) {
-          for (int mm = 0; mm < mc; ++mm) {
-            NT A[9], B[9];
-            for (int e = 0; e < 9; ++e) {
-              NT sa = 0, sb = 0;
-              for (int w = 0; w < NW; ++w) { sa += s_red[w][mm][e]; sb += s_red[w][mm][9 + e]; }
-              A[e] = sa;
-              B[e] = sb;
+              for (int e = 0; e < 9; ++e) rs[r][e] = Qk[9 * (int64_t)jj + e];
+            } else {
+              kernel_entry<T>(a.kp, wl, (T)(xi0 - xsr[3 * jj]), (T)(xi1 - xsr[3 * jj + 1]),
+                              (T)(xi2 - xsr[3 * jj + 2]), rs[r]);
             }
-            NT tr = 0;
-            for (int r = 0; r < 3; ++r)
-              for (int cc = 0; cc < 3; ++cc) tr += A[3 * r + cc] * B[3 * cc + r];
-            if (m0 + mm == k) nu2 = tr; else cross += tr;
+          } else {
+#pragma unroll
+            for (int e = 0; e < 9; ++e) rs[r][e] = 0;
           }
         }
-        __syncthreads();
+#pragma unroll 1
+        for (int m = 0; m < k; ++m) {
+          const T* qmp = a.pool + sh.off[m] + 9 * (int64_t)c;
+          T cv[9];
+#pragma unroll
+          for (int e = 0; e < 9; ++e) cv[e] = sh.qc[9 * m + e];
+          double p[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+          for (int r = 0; r < RCH; ++r) {
+            const int jj = base + 64 * r + lane;
+            T qv[9];
+#pragma unroll
+            for (int e = 0; e < 9; ++e) qv[e] = jj < q ? qmp[9 * (int64_t)jj + e] : T(0);
+#pragma unroll
+            for (int x = 0; x < 3; ++x)
+#pragma unroll
+              for (int y = 0; y < 3; ++y)
+                p[3 * x + y] += (double)rs[r][3 * x] * (double)qv[3 * y] +
+                                (double)rs[r][3 * x + 1] * (double)qv[3 * y + 1] +
+                                (double)rs[r][3 * x + 2] * (double)qv[3 * y + 2];
+            sub_mm<T>(rs[r], cv, qv);
+          }
+          wave_sumv(p);
+          if (lane == m) {
+#pragma unroll
+            for (int e = 0; e < 9; ++e) G[e] += p[e];
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < RCH; ++r) {
+          const int jj = base + 64 * r + lane;
+          if (jj >= q) continue;
+          NT nrm = 0;
+#pragma unroll
+          for (int e = 0; e < 9; ++e) {
+            Qk[9 * (int64_t)jj + e] = rs[r][e];
+            nrm += (NT)rs[r][e] * (NT)rs[r][e];
+          }
+#pragma unroll
+          for (int x = 0; x < 3; ++x)
+#pragma unroll
+            for (int y = 0; y < 3; ++y)
+              SB[3 * x + y] += (double)rs[r][3 * x] * (double)rs[r][3 * y] +
+                               (double)rs[r][3 * x + 1] * (double)rs[r][3 * y + 1] +
+                               (double)rs[r][3 * x + 2] * (double)rs[r][3 * y + 2];
+          if (fuse) {
+            const T* f = a.Fs + 3 * ((int64_t)ns.x + jj);
+            const double f0 = f[0], f1 = f[1], f2 = f[2];
+            SB[9] += (double)rs[r][0] * f0 + (double)rs[r][1] * f1 + (double)rs[r][2] * f2;
+            SB[10] += (double)rs[r][3] * f0 + (double)rs[r][4] * f1 + (double)rs[r][5] * f2;
+            SB[11] += (double)rs[r][6] * f0 + (double)rs[r][7] * f1 + (double)rs[r][8] * f2;
+          }
+          NT sel = a.det_pivot ? det3<NT>(rs[r]) : nrm;
+          bool used = false;
+#pragma unroll 1
+          for (int m = 0; m <= k; ++m) used |= (sh.pj[m] == jj);
+          if (used) sel = -1;
+          if (sel > best || (sel == best && jj < bi)) { best = sel; bi = jj; }
+        }
       }
-      if (tid == 0) {
-        s_lam2 = s_lam2 + nu2 + NT(2) * cross;
-        s_stop = (nu2 <= NT(a.eps2) * s_lam2) ? 1 : 0;
+      wave_sumv(SB);
+      wave_argmax(best, bi);
+      {
+        double d1 = 0, d2 = 0;
+        team_combine<TW>(tr, gx, wit, k, SB, d1, d2, best, bi, G);
       }
-      __syncthreads();
+      const int jn = (bi >= 0 && bi < q) ? bi : -1;   // -1 only when every column is used
+      // B_km = Bhat_m - sum_m' c_m'(i_k) B_m'm (lane m); cross term tr(A_mk B_km)
+      double cr = 0;
+      if (lane < k) {
+#pragma unroll 1
+        for (int m2 = lane; m2 < k; ++m2) {
+          double Bm[9], cd[9];
+          load_hist(hB, lane, m2, Bm);   // B_{m2, lane} = sum_j q_m2(j) q_lane(j)^T
+#pragma unroll
+          for (int e = 0; e < 9; ++e) cd[e] = (double)sh.qc[9 * m2 + e];
+          sub_mm<double>(G, cd, Bm);
+        }
+        const double* s = hA + 9 * (tri(k) + lane);
+#pragma unroll
+        for (int x = 0; x < 3; ++x)
+#pragma unroll
+          for (int y = 0; y < 3; ++y) cr += s[3 * x + y] * G[3 * y + x];
+      }
+      const double cross = wave_sum(cr);
+      team_sync<TW>();   // every wave has read hA before wave 0 writes the next entries
+      if (wit == 0 && lane < k) {
+        double* d = hB + 9 * (tri(k) + lane);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) d[e] = G[e];
+      }
+      if (lead) {
+        double* d = hB + 9 * (tri(k) + k);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) d[e] = SB[e];
+      }
+      double nu2 = 0;
+#pragma unroll
+      for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int y = 0; y < 3; ++y) nu2 += Akk[3 * x + y] * SB[3 * y + x];
+      lam2 = lam2 + nu2 + 2.0 * cross;
+      tp0 = SB[9];
+      tp1 = SB[10];
+      tp2 = SB[11];
+      pending = true;
       rank = k + 1;
-      if (s_stop) { converged = true; break; }
+      if (nu2 <= a.eps2 * lam2) { converged = true; break; }
       if (k + 1 == min(c, q)) { converged = true; break; }
       if (jn < 0) { fallback = true; break; }
       j = jn;
     }
     if (!converged) fallback = true;
-    __syncthreads();
+    team_sync<TW>();
+    if (fuse && !fallback && pending) {
+      // apply of the last term
+      const T* cl = a.pool + sh.off[rank - 1];
+#pragma unroll 1
+      for (int i = tid; i < c; i += stride) {
+        const T* e = cl + 9 * (int64_t)i;
+        ub[3 * i] += (double)e[0] * tp0 + (double)e[1] * tp1 + (double)e[2] * tp2;
+        ub[3 * i + 1] += (double)e[3] * tp0 + (double)e[4] * tp1 + (double)e[5] * tp2;
+        ub[3 * i + 2] += (double)e[6] * tp0 + (double)e[7] * tp1 + (double)e[8] * tp2;
+      }
+    }
     if (fuse && fallback && MF) {
       // dense evaluation of the block's rows (32-row MFMA tiles)
-      for (int t0 = 32 * wv; t0 < c; t0 += 32 * NW) {
+#pragma unroll 1
+      for (int t0 = 32 * wit; t0 < c; t0 += 32 * TW) {
         const int i = t0 + (lane & 31);
         const int ii = i < c ? i : t0;
         const double x0 = xt[3 * ii], x1 = xt[3 * ii + 1], x2 = xt[3 * ii + 2];
         double v0 = 0, v1 = 0, v2 = 0;
+#pragma unroll 1
         for (int jj = 0; jj < q; ++jj) {
           float K[9];
           mfma_entry(fr, a.kp.input_mode, x0 - xsr[3 * jj], x1 - xsr[3 * jj + 1],
@@ -443,9 +701,11 @@ __global__ __launch_bounds__(ACA_T) void k_aca(AcaArgs<T> a) {
     }
     if (fuse && fallback && !MF) {
       // dense evaluation of the block's rows replaces the partial sum
-      for (int i = tid; i < c; i += ACA_T) {
+#pragma unroll 1
+      for (int i = tid; i < c; i += stride) {
         const double x0 = xt[3 * i], x1 = xt[3 * i + 1], x2 = xt[3 * i + 2];
         T v0 = 0, v1 = 0, v2 = 0;
+#pragma unroll 1
         for (int jj = 0; jj < q; ++jj) {
           T K[9];
           kernel_entry<T>(a.kp, wl, (T)(x0 - xsr[3 * jj]), (T)(x1 - xsr[3 * jj + 1]),
@@ -460,26 +720,57 @@ __global__ __launch_bounds__(ACA_T) void k_aca(AcaArgs<T> a) {
         ub[3 * i + 2] = v2;
       }
     }
-    if (tid == 0) {
+    if (lead) {
       a.rank[b] = rank;
       a.flag[b] = fallback ? 1 : 0;
     }
-    for (int t = tid; t < 2 * LMAX_CAP; t += ACA_T) {
-      int m = t % LMAX_CAP;
-      int v = -1;
-      if (m < rank) v = (t < LMAX_CAP) ? s_pi[m] : s_pj[m];
-      a.piv[b * 2 * LMAX_CAP + t] = v;
+    if (wit == 0) {
+#pragma unroll 1
+      for (int t = lane; t < 2 * LMAX_CAP; t += 64) {
+        const int m = t % LMAX_CAP;
+        int v = -1;
+        if (m < rank) v = (t < LMAX_CAP) ? sh.pi[m] : sh.pj[m];
+        a.piv[b * 2 * LMAX_CAP + t] = v;
+      }
     }
+    team_sync<TW>();
   }
+}
+
+// Workgroups of AW waves: first the whole workgroup works as one team on the
+// large blocks order[b0 .. b0 + nbig) (largest first), then every wave works
+// alone on the rest.
+template <class T, int KIND, bool MF>
+__global__ __launch_bounds__(AW_T) void k_aca(AcaArgs<T> a) {
+  __shared__ T wl[(KIND == KIND_MLP && !MF) ? MLP_NP : 1];
+  __shared__ bf16x8 fr[MF ? FR_TOTAL : 1];
+  __shared__ TeamSh<T> shw[AW];
+  __shared__ TeamRed tr;
+  if (MF) {
+    stage_frags(fr, a.frags, AW_T);
+  } else if (KIND == KIND_MLP) {
+    const T* w = (const T*)a.kp.w;
+    for (int i = threadIdx.x; i < MLP_NP; i += AW_T) wl[i] = w[i];
+  }
+  __syncthreads();
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
+  if (a.nbig > 0)
+    aca_worker<T, KIND, MF, AW>(a, wl, fr, shw[0], &tr, wv, (int64_t)blockIdx.x * AW,
+                                a.work_big, a.b0, a.b0 + a.nbig);
+  __syncthreads();
+  aca_worker<T, KIND, MF, 1>(a, wl, fr, shw[wv], &tr, 0, (int64_t)blockIdx.x * AW + wv, a.work,
+                             a.b0 + a.nbig, a.b1);
 }
 
 template <class T>
 void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
                   int64_t b0, int64_t b1, T* pool, int64_t pool_elems, void* pool_top,
-                  int* overflow, int* work, const void* Fs, double* ublk, const int64_t* uoff) {
+                  int* overflow, int* work, int* work_big, int64_t nbig, const void* Fs,
+                  double* ublk, const int64_t* uoff) {
   AcaArgs<T> a;
   a.G = p->G.as<int2>();
   a.nG = p->nG;
+  a.order = lr->order.as<int32_t>();
   a.nodes = t->nodes.as<int4>();
   a.xs = t->xs.as<double>();
   a.kp.kind = k->kind;
@@ -500,6 +791,8 @@ void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
   a.pool_top = (unsigned long long*)pool_top;
   a.overflow = overflow;
   a.work = work;
+  a.work_big = work_big;
+  a.nbig = nbig;
   a.b0 = b0;
   a.b1 = b1;
   a.Fs = (const T*)Fs;
@@ -507,17 +800,39 @@ void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
   a.uoff = uoff;
   a.frags = k->pbf.as<uint4>();
   a.det_pivot = lr->prec != HH_FP64;
-  int grid = (int)std::min<int64_t>(b1 - b0, 4096);
-  if (grid <= 0) return;
-  const bool fp64norm = lr->prec != HH_FP32;
-#define LAUNCH(NT_, KIND_, MF_)                                                             \
-  hipLaunchKernelGGL((k_aca<T, NT_, KIND_, MF_>), dim3(grid), dim3(ACA_T), 0, ctx->stream, a)
+  const int64_t nb = b1 - b0;
+  if (nb <= 0) return;
+  // persistent grid: as many workgroups as stay resident, each wave a worker
+  const void* fn = (k->kind == KIND_MLP && lr->prec == HH_BF16)
+                       ? (const void*)k_aca<float, KIND_MLP, true>
+                       : (k->kind == KIND_MLP ? (const void*)k_aca<T, KIND_MLP, false>
+                                              : (const void*)k_aca<T, KIND_RPY, false>);
+  int per_cu = 0;
+  HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, AW_T, 0));
+  HH_REQUIRE(per_cu > 0, HH_ERR_HIP, "ACA kernel does not fit a compute unit");
+  int64_t grid = (int64_t)per_cu * ctx->n_cu;
+  grid = std::min<int64_t>(grid, std::max<int64_t>(nbig, (nb + AW - 1) / AW));
+  // per worker: Gram history of both sides (l_max (l_max + 1) / 2 3x3 matrices
+  // each), then the cross-wave partials of a workgroup team [AW][64][9]
+  const int64_t half = 9 * ((int64_t)lr->l_max * (lr->l_max + 1) / 2);
+  const int64_t stride = 2 * half + (int64_t)AW * 64 * 9;
+  const int64_t workers = grid * AW;
+  if (lr->gram_workers < workers || lr->gram_stride != stride) {
+    lr->gram.alloc(ctx->stream, std::max<int64_t>(1, workers * stride) * sizeof(double));
+    lr->gram_workers = workers;
+    lr->gram_stride = stride;
+  }
+  a.gram = lr->gram.as<double>();
+  a.gram_stride = stride;
+  a.gram_half = half;
+#define LAUNCH(KIND_, MF_)                                                                  \
+  hipLaunchKernelGGL((k_aca<T, KIND_, MF_>), dim3((unsigned)grid), dim3(AW_T), 0, ctx->stream, a)
   if (k->kind == KIND_MLP && lr->prec == HH_BF16) {
-    if constexpr (sizeof(T) == 4) LAUNCH(double, KIND_MLP, true);
+    if constexpr (sizeof(T) == 4) LAUNCH(KIND_MLP, true);
   } else if (k->kind == KIND_MLP) {
-    if (fp64norm) LAUNCH(double, KIND_MLP, false); else LAUNCH(T, KIND_MLP, false);
+    LAUNCH(KIND_MLP, false);
   } else {
-    if (fp64norm) LAUNCH(double, KIND_RPY, false); else LAUNCH(T, KIND_RPY, false);
+    LAUNCH(KIND_RPY, false);
   }
 #undef LAUNCH
   HIP_OK(hipGetLastError());
@@ -592,6 +907,30 @@ static void block_sizes(hh_ctx ctx, hh_tree t, hh_part p, std::vector<int32_t>& 
   }
 }
 
+// Work order of the ACA launches: within each range [bounds[r], bounds[r+1])
+// the blocks go largest first (by the power of two of c + q, stable); blocks
+// with c + q >= 2^team_cls (the first nbig[r]) are worked on by whole
+// workgroups, the rest by single waves.
+static void upload_order(hh_ctx ctx, hh_lowrank lr, const std::vector<int32_t>& cs,
+                         const std::vector<int32_t>& qs, const std::vector<int64_t>& bounds) {
+  const int64_t nG = (int64_t)cs.size();
+  std::vector<int32_t> ord(std::max<int64_t>(nG, 1));
+  auto cls = [&](int64_t b) { return 31 - __builtin_clz((unsigned)(cs[b] + qs[b])); };
+  lr->nbig.assign(std::max<size_t>(bounds.size(), 2) - 1, 0);
+  for (size_t r = 0; r + 1 < bounds.size(); ++r) {
+    int64_t cnt[33] = {0};
+    for (int64_t b = bounds[r]; b < bounds[r + 1]; ++b) cnt[cls(b)]++;
+    for (int c = ctx->team_cls; c <= 32; ++c) lr->nbig[r] += cnt[c];
+    int64_t pos[33], acc = bounds[r];
+    for (int c = 32; c >= 0; --c) { pos[c] = acc; acc += cnt[c]; }
+    for (int64_t b = bounds[r]; b < bounds[r + 1]; ++b) ord[pos[cls(b)]++] = (int32_t)b;
+  }
+  lr->order.alloc(ctx->stream, ord.size() * sizeof(int32_t));
+  HIP_OK(hipMemcpyAsync(lr->order.p, ord.data(), ord.size() * sizeof(int32_t),
+                        hipMemcpyHostToDevice, ctx->stream));
+  ctx_sync(ctx);
+}
+
 // Plans the ACA: stored factors when they fit the context budget, otherwise
 // streamed batches whose worst-case factor storage fits it (Sec. 3.3.2: a
 // fixed buffer is filled by a group of blocks, applied, then reused).
@@ -615,7 +954,10 @@ void plan_aca(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, int force_streame
   }
   lr->est_elems = est;
   lr->streamed = force_streamed || (double)est * es > 0.5 * (double)ctx->budget_bytes;
-  if (!lr->streamed) return;
+  if (!lr->streamed) {
+    upload_order(ctx, lr, cs, qs, {0, nG});
+    return;
+  }
   // batches: worst-case factor elements + 3 c output doubles per block
   const double cap = 0.5 * (double)ctx->budget_bytes;
   lr->bounds.clear();
@@ -640,6 +982,7 @@ void plan_aca(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, int force_streame
     uoff[b + 1] = uoff[b] + cs[b];
   }
   lr->bounds.push_back(nG);
+  upload_order(ctx, lr, cs, qs, lr->bounds);
   pool_max = std::max(pool_max, pe);
   ub_max = std::max(ub_max, ue);
   lr->pool_elems = std::max<int64_t>(pool_max, 1024);
@@ -667,10 +1010,10 @@ void run_aca_stored(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr
       PhaseTimer timer(ctx, HH_PHASE_ACA);
       if (lr->prec == HH_FP64)
         launch_aca_t<double>(ctx, t, p, k, lr, 0, nG, lr->pool.as<double>(), lr->pool_elems, top,
-                             flags, flags + 1, nullptr, nullptr, nullptr);
+                             flags, flags + 1, flags + 2, lr->nbig[0], nullptr, nullptr, nullptr);
       else
         launch_aca_t<float>(ctx, t, p, k, lr, 0, nG, lr->pool.as<float>(), lr->pool_elems, top,
-                            flags, flags + 1, nullptr, nullptr, nullptr);
+                            flags, flags + 1, flags + 2, lr->nbig[0], nullptr, nullptr, nullptr);
     }
     HIP_OK(hipMemcpyAsync(ctx->pinned, ctx->scratch_flag.p, 8 * sizeof(int64_t),
                           hipMemcpyDeviceToHost, st));
@@ -693,13 +1036,15 @@ void run_aca_stored(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr
 void run_aca_batch(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr, size_t i,
                    const void* Fs, int64_t* counters) {
   int64_t b0 = lr->bounds[i], b1 = lr->bounds[i + 1];
-  int* work = (int*)(counters + 2 * i);
+  int* work = (int*)(counters + 2 * i);   // [0] single waves, [1] workgroups
   int64_t* top = counters + 2 * i + 1;
   int* ovf = (int*)ctx->scratch_flag.p;
   if (lr->prec == HH_FP64)
     launch_aca_t<double>(ctx, t, p, k, lr, b0, b1, lr->pool.as<double>(), lr->pool_elems, top,
-                         ovf, work, Fs, lr->ublk.as<double>(), lr->uoff.as<int64_t>());
+                         ovf, work, work + 1, lr->nbig[i], Fs, lr->ublk.as<double>(),
+                         lr->uoff.as<int64_t>());
   else
     launch_aca_t<float>(ctx, t, p, k, lr, b0, b1, lr->pool.as<float>(), lr->pool_elems, top, ovf,
-                        work, Fs, lr->ublk.as<double>(), lr->uoff.as<int64_t>());
+                        work, work + 1, lr->nbig[i], Fs, lr->ublk.as<double>(),
+                        lr->uoff.as<int64_t>());
 }

@@ -183,6 +183,7 @@ hh_status hh_ctx_create(int device, void* stream, hh_ctx* out) {
     HIP_OK(hipSetDevice(device));
     ctx->device = device;
     ctx->stream = (hipStream_t)stream;
+    HIP_OK(hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, device));
     // keep freed blocks in the stream-ordered pool for reuse across steps
     hipMemPool_t pool;
     if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
@@ -231,6 +232,16 @@ hh_status hh_ctx_set_budget(hh_ctx ctx, size_t bytes) {
   HH_API_BEGIN(ctx)
   HH_REQUIRE(bytes >= 4096, HH_ERR_INVALID_ARG, "budget must be at least 4096 bytes");
   ctx->budget_bytes = bytes;
+  HH_API_END(ctx)
+}
+
+hh_status hh_ctx_set_team_min(hh_ctx ctx, int32_t team_min) {
+  HH_API_BEGIN(ctx)
+  HH_REQUIRE(team_min >= 64 && team_min <= (1 << 30), HH_ERR_INVALID_ARG,
+             "team_min must be in [64, 2^30]");
+  int cls = 0;
+  while ((1 << cls) < team_min) ++cls;
+  ctx->team_cls = cls;
   HH_API_END(ctx)
 }
 

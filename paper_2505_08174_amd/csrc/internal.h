@@ -54,6 +54,7 @@ struct PhaseRec {
 
 struct hh_ctx_s {
   int device = 0;
+  int n_cu = 1;                // compute units of the device
   hipStream_t stream = nullptr;
   std::string last_error;
   DevBuf scratch_flag;   // small device scratch for readbacks (64 x int64)
@@ -62,6 +63,7 @@ struct hh_ctx_s {
   std::vector<PhaseRec> pending;
   std::vector<hipEvent_t> event_pool;
   size_t budget_bytes = 0;     // device memory the ACA may use for factors
+  int team_cls = 12;           // blocks with c + q >= 2^team_cls go to whole workgroups
   double phase_ms[HH_NPHASE] = {0};
   int64_t phase_cnt[HH_NPHASE] = {0};
 };
@@ -171,6 +173,11 @@ struct hh_lowrank_s {
   int64_t ub_elems = 0;          // largest batch sum of c
   DevBuf uoff;                   // int64 [nG+1] prefix sums of c
   DevBuf ublk;                   // double [ub_elems][3]
+  DevBuf order;                  // int32 [nG] ACA work order (largest blocks first)
+  std::vector<int64_t> nbig;     // per launch range: blocks for whole workgroups
+  // Gram history of the block being approximated, one slot per ACA worker
+  DevBuf gram;
+  int64_t gram_workers = 0, gram_stride = 0;
 };
 
 // ------------------------------------------------------------- helpers

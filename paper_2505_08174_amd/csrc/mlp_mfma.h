@@ -85,6 +85,9 @@ __device__ __forceinline__ void hidden_layer(const bf16x8* __restrict__ fr, int 
 template <bool ACC>
 __device__ __forceinline__ void mlp_tile_bf16(const bf16x8* __restrict__ fr, float v0, float v1,
                                               float v2, float o[9]) {
+  // the fragments are re-read from LDS for every tile: hoisting them out of
+  // a caller's loop would pin 192 VGPRs and cut the occupancy to one wave
+  __asm__ volatile("" ::: "memory");
   const int lane = threadIdx.x & 63;
   const bool h1 = lane >= 32;
   const __bf16 z = (__bf16)0.0f, one = (__bf16)1.0f;
