@@ -10,10 +10,14 @@ Prints ONE JSON line (rank 0). The roofline object is for the dominant kernel
 (largest device time per step), with its average launch duration measured
 live with HIP events on the library's stream; the cpu_baseline object is the
 plain FP64 CPU oracle on a time-bounded sample of rows of the same workload.
+
+--copy-calibration runs only a plain device copy of a known size (for
+scaling the HBM byte counters of a profiler run) and prints its size.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -29,6 +33,14 @@ sys.path.insert(0, ROOT)
 PEAK = {"hbm_GBs": 8000.0, "bf16_TFs": 2500.0, "fp32_TFs": 157.3, "fp64_TFs": 78.6}
 MLP_MAC = 3 * 64 + 64 * 64 + 64 * 64 + 64 * 9      # 8,960 multiply-adds per kernel query
 MLP_FLOP = 2 * MLP_MAC
+MLP_TANH = 3 * 64                                  # activations per kernel query
+# tanh = 1 - 2 / (exp(2x) + 1): two transcendental ops; at a quarter of the
+# FP32 lane rate that is 8 tanh per clock per CU
+TANH_PER_CLK_CU = 8
+CU, CLK = 256, 2.4e9
+# sources whose change invalidates the stored HBM traffic of a kernel
+KERNEL_SOURCES = {"k_aca": ["aca.hip", "mlp_mfma.h", "devmath.h", "internal.h"],
+                  "k_near": ["near_mfma.hip", "near.hip", "mlp_mfma.h", "devmath.h", "internal.h"]}
 
 
 def log(*a):
@@ -38,15 +50,49 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="precision_1m")
     ap.add_argument("--n", type=int, default=None, help="override the workload's N")
     ap.add_argument("--prec", default=None, help="override precision (fp64, fp32, bf16)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--l-max", type=int, default=48)
+    ap.add_argument("--copy-calibration", action="store_true")
     return ap.parse_args()
+
+
+def sources_sha(kernel):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2505_08174_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel, workload):
+    """HBM bytes per launch from the committed profiler counters, if they were
+    taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.txt" % (kernel, workload))
+    try:
+        with open(path) as fh:
+            rec = json.loads(fh.read().split("\n---\n")[0])
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != sources_sha(kernel):
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def copy_calibration():
+    import torch
+    nbytes = 1 << 30
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}))
 
 
 def cpu_baseline(X, F, kern_cfg, U_gpu, budget_s):
@@ -83,6 +129,9 @@ def cpu_baseline(X, F, kern_cfg, U_gpu, budget_s):
 
 def main():
     a = parse()
+    if a.copy_calibration:
+        copy_calibration()
+        return
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % a.gpus, file=sys.stderr)
@@ -137,25 +186,34 @@ def main():
     pairs_near = ps["near_pairs"] - n          # self pairs are skipped
     per_step = {k: v[0] / a.steps for k, v in ph.items()}
     log("phases ms/step:", {k: round(v, 3) for k, v in per_step.items()})
-    # dominant kernel
+    # dominant kernel: kernel queries (pairs) per launch x the MLP's flops
     dom = max(("near", "aca"), key=lambda k: per_step[k])
-    if dom == "near":
-        flop = pairs_near * MLP_FLOP if cfg["kernel"] == "mlp" else pairs_near * 40
-        launch_ms = ph["near"][0] / max(1, ph["near"][1])
-    else:
-        flop = li["samples"] * MLP_FLOP if cfg["kernel"] == "mlp" else li["samples"] * 40
-        launch_ms = ph["aca"][0] / max(1, ph["aca"][1])
-    achieved = flop / (launch_ms * 1e-3) / 1e12
+    queries = pairs_near if dom == "near" else li["samples"]   # per step
+    launches = ph[dom][1] / a.steps                            # per step
+    launch_ms = ph[dom][0] / max(1, ph[dom][1])
+    per_query = MLP_FLOP if cfg["kernel"] == "mlp" else 40
+    flop_launch = queries * per_query / launches
+    achieved = flop_launch / (launch_ms * 1e-3) / 1e12
     if prec == "bf16":
         bound, peak = "mfma", PEAK["bf16_TFs"]
     elif prec == "fp32":
         bound, peak = "alu", PEAK["fp32_TFs"]
     else:
         bound, peak = "alu", PEAK["fp64_TFs"]
-    roof = {"bound": bound, "kernel": "k_near" if dom == "near" else "k_aca",
+    kname = "k_near" if dom == "near" else "k_aca"
+    traffic = stored_traffic(kname, a.workload)
+    roof = {"bound": bound, "kernel": kname,
             "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 5), "traffic": None,
-            "launch_ms": round(launch_ms, 4), "algorithmic_flop_per_launch": flop}
+            "frac": round(achieved / peak, 5), "traffic": traffic,
+            "launch_ms": round(launch_ms, 4), "launches_per_step": launches,
+            "algorithmic_flop_per_launch": flop_launch,
+            "queries_per_launch": queries / launches}
+    if cfg["kernel"] == "mlp":
+        # co-bound: the 192 tanh per query on the VALU
+        ceil = CU * CLK * TANH_PER_CLK_CU / MLP_TANH
+        qps = queries / launches / (launch_ms * 1e-3)
+        roof["tanh_ceiling_queries_per_s"] = ceil
+        roof["frac_tanh"] = round(qps / ceil, 5)
     out = {
         "metric": "H-matvec ms/step and particles/s at N=1M, rel err vs FP64 dense; MFMA%, HBM GB/s",
         "value": n / (ms * 1e-3), "unit": "particles/s", "n_gpus": 1, "steps": a.steps,
