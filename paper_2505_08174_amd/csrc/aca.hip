@@ -50,6 +50,8 @@ struct AcaArgs {
   int64_t* fptr;     // [nG][LMAX_CAP]
   T* pool;
   int64_t pool_elems;
+  T* arena;             // per-wave factor arenas (streamed mode, single-wave blocks)
+  int64_t arena_elems;  // elements per arena
   unsigned long long* pool_top;
   int* overflow;
   int* work;         // dynamic block counter (blocks worked on by single waves)
@@ -58,11 +60,11 @@ struct AcaArgs {
   int64_t b0, b1;    // block range of this launch
   // fused apply (streamed mode): Fs != nullptr
   const T* Fs;       // sorted forces
-  double* ublk;      // per-block output rows [c][3], at uoff[b] - uoff[b0]
-  const int64_t* uoff;
+  double* ublk;      // per-block output rows [c][3], at uoff[pos] - uoff[b0]
+  const int64_t* uoff;   // prefix sums of c over the work order (streamed mode)
   const uint4* frags;   // BF16 MFMA weight fragments (MF kernels)
   int det_pivot;        // pivot magnitude |det| (else squared Frobenius norm)
-  double* gram;         // Gram history A, B (gram_half doubles each) and cross-wave
+  double* gram;         // Gram history A (gram_half doubles) and cross-wave
   int64_t gram_stride;  // partials, gram_stride doubles per worker
   int64_t gram_half;
 };
@@ -151,6 +153,17 @@ __device__ __forceinline__ void load_hist(const double* __restrict__ h, int m1, 
   }
 }
 
+// Entries 9 i .. 9 i + 8 of f for the rows i = i0 + 64 r (r < RCH), zero past n.
+template <class T>
+__device__ __forceinline__ void load_rows(const T* __restrict__ f, int i0, int n, T (&v)[RCH][9]) {
+#pragma unroll
+  for (int r = 0; r < RCH; ++r) {
+    const int i = i0 + 64 * r;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) v[r][e] = i < n ? f[9 * (int64_t)i + e] : T(0);
+  }
+}
+
 // Scratch of one worker team (TW waves) for the block it approximates.
 template <class T>
 struct TeamSh {
@@ -158,6 +171,7 @@ struct TeamSh {
   int64_t off[LMAX_CAP];  // pool offset of factor m
   int pi[LMAX_CAP];
   int pj[LMAX_CAP + 1];
+  double am[LMAX_CAP * 9];  // A_mk = sum_i c_m(i)^T c_k(i), m < k (row pass)
   int64_t bo;             // broadcast: claimed block, pool offset
   int ovf;                // broadcast: pool overflow
 };
@@ -265,8 +279,10 @@ __device__ __forceinline__ void team_combine(TeamRed* tr, double* gx, int wit, i
 //   pivot i_k, c_k = a P^-1;
 //   A_mk = sum_i c_m(i)^T c_k(i) = (Ghat_m - sum_{m<=m'<k} A_mm' q_m'(j_k)) P^-1
 //     from the stored Gram history A_mm' (lane m works on m);
-//   row pass likewise: q_k(j) = h(j) - sum_m c_m(i_k) q_m(j),
-//     B_km = sum_j q_k(j) q_m(j)^T = Bhat_m - sum_{m<=m'<k} c_m'(i_k) B_m'm;
+//   row pass: q_k(j) = h(j) - sum_m c_m(i_k) q_m(j), and in the same pass
+//     V(j) = sum_{m<k} A_mk^T q_m(j), so that the cross terms
+//     sum_{m<k} tr(A_mk B_km) = sum_j <V(j), q_k(j)>_F (B_km = sum_j q_k(j) q_m(j)^T)
+//     take one scalar reduction; B_kk = sum_j q_k(j) q_k(j)^T;
 //   nu^2 = tr(A_kk B_kk), lambda^2 += nu^2 + 2 sum_{m<k} tr(A_mk B_km).
 // So the Gram terms cost no extra pass over the factors. Every wave of a team
 // computes the per-step scalars itself from the same combined values, so all
@@ -282,15 +298,19 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
   const int stride = 64 * TW;   // threads of the team
   const int tid = 64 * wit + lane;
   double* hA = a.gram + slot * a.gram_stride;
-  double* hB = hA + a.gram_half;
-  double* gx = hB + a.gram_half;   // cross-wave partials, [AW][64][9]
+  double* gx = hA + a.gram_half;   // cross-wave partials, [AW][64][9]
+  // factor storage: a wave's own arena (offsets restart with every block) or
+  // the shared pool (bump-allocated)
+  const bool own = TW == 1 && a.arena != nullptr;
+  T* const fb = own ? a.arena + slot * a.arena_elems : a.pool;
 #pragma unroll 1
   for (;;) {
     if (lead) sh.bo = atomicAdd(counter, 1);
     team_sync<TW>();
     const int64_t sb = sh.bo;
     if (r0 + sb >= r1) break;
-    const int64_t b = a.order[r0 + sb];
+    const int64_t pos = r0 + sb;
+    const int64_t b = a.order[pos];
     const int2 g2 = a.G[b];
     const int4 nt = a.nodes[g2.x], ns = a.nodes[g2.y];
     const int c = nt.y - nt.x, q = ns.y - ns.x;
@@ -302,7 +322,7 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
     bool converged = false, fallback = false, pending = false;
     double lam2 = 0;
     const bool fuse = a.Fs != nullptr;
-    double* ub = fuse ? a.ublk + 3 * (a.uoff[b] - a.uoff[a.b0]) : nullptr;
+    double* ub = fuse ? a.ublk + 3 * (a.uoff[pos] - a.uoff[a.b0]) : nullptr;
     if (fuse)
 #pragma unroll 1
       for (int i = tid; i < 3 * c; i += stride) ub[i] = 0.0;
@@ -312,12 +332,16 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
       team_sync<TW>();   // sh.bo and sh.qc of the previous step are consumed
       if (lead) {
         const unsigned long long need = 9ull * (unsigned long long)(c + q);
-        const unsigned long long o = atomicAdd(a.pool_top, need);
+        unsigned long long o;
         int ovf = 0;
-        if ((int64_t)(o + need) > a.pool_elems) {
-          atomicOr(a.overflow, 1);
-          ovf = 1;
+        if (own) {
+          o = (unsigned long long)k * need;
+          ovf = (int64_t)(o + need) > a.arena_elems;
+        } else {
+          o = atomicAdd(a.pool_top, need);
+          ovf = (int64_t)(o + need) > a.pool_elems;
         }
+        if (ovf) atomicOr(a.overflow, 1);
         sh.bo = (int64_t)o;
         sh.ovf = ovf;
         sh.off[k] = (int64_t)o;
@@ -330,9 +354,9 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
 #pragma unroll 1
       for (int t = tid; t < 9 * k; t += stride) {
         const int m = t / 9, e = t - 9 * m;
-        sh.qc[t] = a.pool[sh.off[m] + 9 * (int64_t)c + 9 * (int64_t)j + e];
+        sh.qc[t] = fb[sh.off[m] + 9 * (int64_t)c + 9 * (int64_t)j + e];
       }
-      T* Ck = a.pool + offv;
+      T* Ck = fb + offv;
       T* Qk = Ck + 9 * (int64_t)c;
       const double yj0 = xsr[3 * j], yj1 = xsr[3 * j + 1], yj2 = xsr[3 * j + 2];
       if (MF) sample_mfma<TW>(fr, a.kp.input_mode, xt, c, yj0, yj1, yj2, 1.0, (float*)Ck, wit);
@@ -367,9 +391,17 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
             graw = g2s > graw ? g2s : graw;
           }
         }
+        // c_m(i) of the next m is loaded while m is worked on
+        T cn[RCH][9];
+        if (k > 0) load_rows<T>(fb + sh.off[0], base + lane, c, cn);
 #pragma unroll 1
         for (int m = 0; m < k; ++m) {
-          const T* cm = a.pool + sh.off[m];
+          T cc[RCH][9];
+#pragma unroll
+          for (int r = 0; r < RCH; ++r)
+#pragma unroll
+            for (int e = 0; e < 9; ++e) cc[r][e] = cn[r][e];
+          if (m + 1 < k) load_rows<T>(fb + sh.off[m + 1], base + lane, c, cn);
           T qv[9];
 #pragma unroll
           for (int e = 0; e < 9; ++e) qv[e] = sh.qc[9 * m + e];
@@ -377,9 +409,7 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
 #pragma unroll
           for (int r = 0; r < RCH; ++r) {
             const int i = base + 64 * r + lane;
-            T cv[9];
-#pragma unroll
-            for (int e = 0; e < 9; ++e) cv[e] = i < c ? cm[9 * (int64_t)i + e] : T(0);
+            const T* cv = cc[r];
 #pragma unroll
             for (int x = 0; x < 3; ++x)
 #pragma unroll
@@ -488,7 +518,10 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
         if (wit == 0) {
           double* d = hA + 9 * (tri(k) + lane);
 #pragma unroll
-          for (int e = 0; e < 9; ++e) d[e] = Amk[e];
+          for (int e = 0; e < 9; ++e) {
+            d[e] = Amk[e];
+            sh.am[9 * lane + e] = Amk[e];
+          }
         }
       }
       if (lead) {
@@ -517,7 +550,7 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
 #pragma unroll 1
       for (int t = tid; t < 9 * k; t += stride) {
         const int m = t / 9, e = t - 9 * m;
-        sh.qc[t] = a.pool[sh.off[m] + 9 * (int64_t)ik + e];
+        sh.qc[t] = fb[sh.off[m] + 9 * (int64_t)ik + e];
       }
       const double xi0 = xt[3 * ik], xi1 = xt[3 * ik + 1], xi2 = xt[3 * ik + 2];
       if (MF) sample_mfma<TW>(fr, a.kp.input_mode, xsr, q, xi0, xi1, xi2, -1.0, (float*)Qk, wit);
@@ -525,11 +558,11 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
       // ---- row pass: residual, Bhat, next column pivot, sum q_k q_k^T, t_k
       best = -1;
       bi = 0x7fffffff;
-      double SB[12];   // B_kk (9), then t_k (3)
+      // B_kk = sum_j q_k(j) q_k(j)^T (9), t_k (3), cross term (1):
+      // sum_{m<k} tr(A_mk B_km) = sum_j < sum_{m<k} A_mk^T q_m(j), q_k(j) >_F
+      double SB[13];
 #pragma unroll
-      for (int e = 0; e < 12; ++e) SB[e] = 0;
-#pragma unroll
-      for (int e = 0; e < 9; ++e) G[e] = 0;   // now Bhat_m
+      for (int e = 0; e < 13; ++e) SB[e] = 0;
 #pragma unroll 1
       for (int base = CH * wit; base < q; base += CH * TW) {
         T rs[RCH][9];
@@ -549,32 +582,39 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
             for (int e = 0; e < 9; ++e) rs[r][e] = 0;
           }
         }
+        double V[RCH][9];   // sum_{m<k} A_mk^T q_m(j)
+#pragma unroll
+        for (int r = 0; r < RCH; ++r)
+#pragma unroll
+          for (int e = 0; e < 9; ++e) V[r][e] = 0;
+        // q_m(j) of the next m is loaded while m is worked on
+        T qn[RCH][9];
+        if (k > 0) load_rows<T>(fb + sh.off[0] + 9 * (int64_t)c, base + lane, q, qn);
 #pragma unroll 1
         for (int m = 0; m < k; ++m) {
-          const T* qmp = a.pool + sh.off[m] + 9 * (int64_t)c;
-          T cv[9];
+          T qq[RCH][9];
 #pragma unroll
-          for (int e = 0; e < 9; ++e) cv[e] = sh.qc[9 * m + e];
-          double p[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+          for (int r = 0; r < RCH; ++r)
+#pragma unroll
+            for (int e = 0; e < 9; ++e) qq[r][e] = qn[r][e];
+          if (m + 1 < k) load_rows<T>(fb + sh.off[m + 1] + 9 * (int64_t)c, base + lane, q, qn);
+          T cv[9];
+          double am[9];
+#pragma unroll
+          for (int e = 0; e < 9; ++e) {
+            cv[e] = sh.qc[9 * m + e];
+            am[e] = sh.am[9 * m + e];
+          }
 #pragma unroll
           for (int r = 0; r < RCH; ++r) {
-            const int jj = base + 64 * r + lane;
-            T qv[9];
-#pragma unroll
-            for (int e = 0; e < 9; ++e) qv[e] = jj < q ? qmp[9 * (int64_t)jj + e] : T(0);
+            const T* qv = qq[r];
 #pragma unroll
             for (int x = 0; x < 3; ++x)
 #pragma unroll
               for (int y = 0; y < 3; ++y)
-                p[3 * x + y] += (double)rs[r][3 * x] * (double)qv[3 * y] +
-                                (double)rs[r][3 * x + 1] * (double)qv[3 * y + 1] +
-                                (double)rs[r][3 * x + 2] * (double)qv[3 * y + 2];
+                V[r][3 * x + y] += am[x] * (double)qv[y] + am[3 + x] * (double)qv[3 + y] +
+                                   am[6 + x] * (double)qv[6 + y];
             sub_mm<T>(rs[r], cv, qv);
-          }
-          wave_sumv(p);
-          if (lane == m) {
-#pragma unroll
-            for (int e = 0; e < 9; ++e) G[e] += p[e];
           }
         }
 #pragma unroll
@@ -594,6 +634,8 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
               SB[3 * x + y] += (double)rs[r][3 * x] * (double)rs[r][3 * y] +
                                (double)rs[r][3 * x + 1] * (double)rs[r][3 * y + 1] +
                                (double)rs[r][3 * x + 2] * (double)rs[r][3 * y + 2];
+#pragma unroll
+          for (int e = 0; e < 9; ++e) SB[12] += V[r][e] * (double)rs[r][e];
           if (fuse) {
             const T* f = a.Fs + 3 * ((int64_t)ns.x + jj);
             const double f0 = f[0], f1 = f[1], f2 = f[2];
@@ -613,43 +655,18 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
       wave_argmax(best, bi);
       {
         double d1 = 0, d2 = 0;
-        team_combine<TW>(tr, gx, wit, k, SB, d1, d2, best, bi, G);
+        team_combine<TW>(tr, gx, wit, 0, SB, d1, d2, best, bi, G);
       }
       const int jn = (bi >= 0 && bi < q) ? bi : -1;   // -1 only when every column is used
-      // B_km = Bhat_m - sum_m' c_m'(i_k) B_m'm (lane m); cross term tr(A_mk B_km)
-      double cr = 0;
-      if (lane < k) {
-#pragma unroll 1
-        for (int m2 = lane; m2 < k; ++m2) {
-          double Bm[9], cd[9];
-          load_hist(hB, lane, m2, Bm);   // B_{m2, lane} = sum_j q_m2(j) q_lane(j)^T
-#pragma unroll
-          for (int e = 0; e < 9; ++e) cd[e] = (double)sh.qc[9 * m2 + e];
-          sub_mm<double>(G, cd, Bm);
-        }
-        const double* s = hA + 9 * (tri(k) + lane);
+      const double cross = SB[12];
+      double nu2 = 0;
+      {
+        const double* akk = hA + 9 * (tri(k) + k);   // A_kk, written by the lead lane
 #pragma unroll
         for (int x = 0; x < 3; ++x)
 #pragma unroll
-          for (int y = 0; y < 3; ++y) cr += s[3 * x + y] * G[3 * y + x];
+          for (int y = 0; y < 3; ++y) nu2 += akk[3 * x + y] * SB[3 * y + x];
       }
-      const double cross = wave_sum(cr);
-      team_sync<TW>();   // every wave has read hA before wave 0 writes the next entries
-      if (wit == 0 && lane < k) {
-        double* d = hB + 9 * (tri(k) + lane);
-#pragma unroll
-        for (int e = 0; e < 9; ++e) d[e] = G[e];
-      }
-      if (lead) {
-        double* d = hB + 9 * (tri(k) + k);
-#pragma unroll
-        for (int e = 0; e < 9; ++e) d[e] = SB[e];
-      }
-      double nu2 = 0;
-#pragma unroll
-      for (int x = 0; x < 3; ++x)
-#pragma unroll
-        for (int y = 0; y < 3; ++y) nu2 += Akk[3 * x + y] * SB[3 * y + x];
       lam2 = lam2 + nu2 + 2.0 * cross;
       tp0 = SB[9];
       tp1 = SB[10];
@@ -665,7 +682,7 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
     team_sync<TW>();
     if (fuse && !fallback && pending) {
       // apply of the last term
-      const T* cl = a.pool + sh.off[rank - 1];
+      const T* cl = fb + sh.off[rank - 1];
 #pragma unroll 1
       for (int i = tid; i < c; i += stride) {
         const T* e = cl + 9 * (int64_t)i;
@@ -812,10 +829,10 @@ void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
   HH_REQUIRE(per_cu > 0, HH_ERR_HIP, "ACA kernel does not fit a compute unit");
   int64_t grid = (int64_t)per_cu * ctx->n_cu;
   grid = std::min<int64_t>(grid, std::max<int64_t>(nbig, (nb + AW - 1) / AW));
-  // per worker: Gram history of both sides (l_max (l_max + 1) / 2 3x3 matrices
-  // each), then the cross-wave partials of a workgroup team [AW][64][9]
+  // per worker: Gram history A (l_max (l_max + 1) / 2 3x3 matrices), then the
+  // cross-wave partials of a workgroup team [AW][64][9]
   const int64_t half = 9 * ((int64_t)lr->l_max * (lr->l_max + 1) / 2);
-  const int64_t stride = 2 * half + (int64_t)AW * 64 * 9;
+  const int64_t stride = half + (int64_t)AW * 64 * 9;
   const int64_t workers = grid * AW;
   if (lr->gram_workers < workers || lr->gram_stride != stride) {
     lr->gram.alloc(ctx->stream, std::max<int64_t>(1, workers * stride) * sizeof(double));
@@ -825,6 +842,16 @@ void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
   a.gram = lr->gram.as<double>();
   a.gram_stride = stride;
   a.gram_half = half;
+  a.arena = nullptr;
+  a.arena_elems = 0;
+  if (Fs && lr->arena_elems > 0) {
+    if (lr->arena_workers < workers) {
+      lr->arena.alloc(ctx->stream, workers * lr->arena_elems * sizeof(T));
+      lr->arena_workers = workers;
+    }
+    a.arena = lr->arena.as<T>();
+    a.arena_elems = lr->arena_elems;
+  }
 #define LAUNCH(KIND_, MF_)                                                                  \
   hipLaunchKernelGGL((k_aca<T, KIND_, MF_>), dim3((unsigned)grid), dim3(AW_T), 0, ctx->stream, a)
   if (k->kind == KIND_MLP && lr->prec == HH_BF16) {
@@ -907,33 +934,40 @@ static void block_sizes(hh_ctx ctx, hh_tree t, hh_part p, std::vector<int32_t>& 
   }
 }
 
-// Work order of the ACA launches: within each range [bounds[r], bounds[r+1])
-// the blocks go largest first (by the power of two of c + q, stable); blocks
-// with c + q >= 2^team_cls (the first nbig[r]) are worked on by whole
-// workgroups, the rest by single waves.
-static void upload_order(hh_ctx ctx, hh_lowrank lr, const std::vector<int32_t>& cs,
-                         const std::vector<int32_t>& qs, const std::vector<int64_t>& bounds) {
-  const int64_t nG = (int64_t)cs.size();
-  std::vector<int32_t> ord(std::max<int64_t>(nG, 1));
-  auto cls = [&](int64_t b) { return 31 - __builtin_clz((unsigned)(cs[b] + qs[b])); };
-  lr->nbig.assign(std::max<size_t>(bounds.size(), 2) - 1, 0);
-  for (size_t r = 0; r + 1 < bounds.size(); ++r) {
-    int64_t cnt[33] = {0};
-    for (int64_t b = bounds[r]; b < bounds[r + 1]; ++b) cnt[cls(b)]++;
-    for (int c = ctx->team_cls; c <= 32; ++c) lr->nbig[r] += cnt[c];
-    int64_t pos[33], acc = bounds[r];
-    for (int c = 32; c >= 0; --c) { pos[c] = acc; acc += cnt[c]; }
-    for (int64_t b = bounds[r]; b < bounds[r + 1]; ++b) ord[pos[cls(b)]++] = (int32_t)b;
-  }
-  lr->order.alloc(ctx->stream, ord.size() * sizeof(int32_t));
-  HIP_OK(hipMemcpyAsync(lr->order.p, ord.data(), ord.size() * sizeof(int32_t),
-                        hipMemcpyHostToDevice, ctx->stream));
-  ctx_sync(ctx);
+static inline int size_cls(int32_t c, int32_t q) {
+  return 31 - __builtin_clz((unsigned)(c + q));
 }
 
-// Plans the ACA: stored factors when they fit the context budget, otherwise
-// streamed batches whose worst-case factor storage fits it (Sec. 3.3.2: a
-// fixed buffer is filled by a group of blocks, applied, then reused).
+// Appends the blocks `blk` to the work order, largest first (by the power of
+// two of c + q, stable).
+static void append_desc(const std::vector<int32_t>& cs, const std::vector<int32_t>& qs,
+                        const std::vector<int32_t>& blk, std::vector<int32_t>& ord) {
+  int64_t cnt[33] = {0};
+  for (int32_t b : blk) cnt[size_cls(cs[b], qs[b])]++;
+  int64_t pos[33], acc = (int64_t)ord.size();
+  for (int c = 32; c >= 0; --c) { pos[c] = acc; acc += cnt[c]; }
+  ord.resize(acc);
+  for (int32_t b : blk) ord[pos[size_cls(cs[b], qs[b])]++] = b;
+}
+
+static void upload_i32(hh_ctx ctx, DevBuf& d, const std::vector<int32_t>& v) {
+  d.alloc(ctx->stream, std::max<size_t>(v.size(), 1) * sizeof(int32_t));
+  if (!v.empty())
+    HIP_OK(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                          ctx->stream));
+}
+
+// Plans the ACA. Each launch works on a range of the work order: first the
+// large blocks (c + q >= 2^team_cls, whole workgroups, largest first), then
+// the small ones (single waves, largest first).
+// Stored mode: one launch over all blocks; the factors stay in the pool.
+// Streamed mode (factors would not fit the context budget; Sec. 3.3.2: a
+// fixed buffer is filled by a group of blocks, applied, then reused): the
+// large blocks go in batches whose worst-case factor storage fits half the
+// budget (bump-allocated in a shared pool); a small block only lives while
+// its wave works on it, so it takes a fixed per-wave arena and the small
+// blocks are split only by the size of their output rows. Launch r takes
+// large batch r and small chunk r.
 void plan_aca(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, int force_streamed) {
   hipStream_t st = ctx->stream;
   int64_t nG = p->nG;
@@ -945,50 +979,92 @@ void plan_aca(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, int force_streame
   std::vector<int32_t> cs, qs;
   block_sizes(ctx, t, p, cs, qs);
   const size_t es = lr->prec == HH_FP64 ? 8 : 4;
-  int64_t est = 0, worst = 0;
+  int64_t est = 0;
+  std::vector<int32_t> big, small;
+  int64_t arena = 0;
   for (int64_t b = 0; b < nG; ++b) {
-    int64_t cq = (int64_t)cs[b] + qs[b];
-    int64_t kc = std::min<int64_t>(std::min(cs[b], qs[b]), lr->l_max);
+    const int64_t cq = (int64_t)cs[b] + qs[b];
+    const int64_t kc = std::min<int64_t>(std::min(cs[b], qs[b]), lr->l_max);
     est += 9 * cq * std::min<int64_t>(kc, 20);
-    worst += 9 * cq * kc;
+    if (size_cls(cs[b], qs[b]) >= ctx->team_cls) {
+      big.push_back((int32_t)b);
+    } else {
+      small.push_back((int32_t)b);
+      arena = std::max(arena, 9 * cq * kc);
+    }
   }
   lr->est_elems = est;
   lr->streamed = force_streamed || (double)est * es > 0.5 * (double)ctx->budget_bytes;
+  std::vector<int32_t> ord;
+  ord.reserve(std::max<int64_t>(nG, 1));
+  lr->bounds.assign(1, 0);
+  lr->nbig.clear();
   if (!lr->streamed) {
-    upload_order(ctx, lr, cs, qs, {0, nG});
+    append_desc(cs, qs, big, ord);
+    append_desc(cs, qs, small, ord);
+    lr->bounds.push_back(nG);
+    lr->nbig.push_back((int64_t)big.size());
+    lr->arena_elems = 0;
+    upload_i32(ctx, lr->order, ord);
+    ctx_sync(ctx);
     return;
   }
-  // batches: worst-case factor elements + 3 c output doubles per block
+  // large blocks: batches by worst-case factor storage
   const double cap = 0.5 * (double)ctx->budget_bytes;
-  lr->bounds.clear();
-  lr->bounds.push_back(0);
-  std::vector<int64_t> uoff(nG + 1, 0);
+  std::vector<std::vector<int32_t>> bb(1), sb(1);
   double acc = 0;
-  int64_t pool_max = 0, ub_max = 0, pe = 0, ue = 0;
-  for (int64_t b = 0; b < nG; ++b) {
-    int64_t cq = (int64_t)cs[b] + qs[b];
-    int64_t kc = std::min<int64_t>(std::min(cs[b], qs[b]), lr->l_max);
-    double bytes = (double)(9 * cq * kc) * es + 24.0 * cs[b];
+  int64_t pe = 0, pool_max = 0;
+  for (int32_t b : big) {
+    const int64_t cq = (int64_t)cs[b] + qs[b];
+    const int64_t kc = std::min<int64_t>(std::min(cs[b], qs[b]), lr->l_max);
+    const double bytes = (double)(9 * cq * kc) * es + 24.0 * cs[b];
     if (acc > 0 && acc + bytes > cap) {
-      lr->bounds.push_back(b);
+      bb.emplace_back();
       pool_max = std::max(pool_max, pe);
-      ub_max = std::max(ub_max, ue);
       acc = 0;
-      pe = ue = 0;
+      pe = 0;
     }
+    bb.back().push_back(b);
     acc += bytes;
     pe += 9 * cq * kc;
-    ue += cs[b];
-    uoff[b + 1] = uoff[b] + cs[b];
   }
-  lr->bounds.push_back(nG);
-  upload_order(ctx, lr, cs, qs, lr->bounds);
   pool_max = std::max(pool_max, pe);
-  ub_max = std::max(ub_max, ue);
+  // small blocks: chunks by output rows (24 bytes per row)
+  const int64_t rows_cap = std::max<int64_t>(1, (int64_t)(0.2 * (double)ctx->budget_bytes / 24.0));
+  int64_t rows = 0;
+  for (int32_t b : small) {
+    if (rows > 0 && rows + cs[b] > rows_cap) {
+      sb.emplace_back();
+      rows = 0;
+    }
+    sb.back().push_back(b);
+    rows += cs[b];
+  }
+  const size_t L = std::max(bb.size(), sb.size());
+  std::vector<int32_t> lid(std::max<int64_t>(nG, 1)), pos(std::max<int64_t>(nG, 1));
+  std::vector<int64_t> uoff(1, 0);
+  int64_t ub_max = 0;
+  for (size_t r = 0; r < L; ++r) {
+    const size_t r0 = ord.size();
+    if (r < bb.size()) append_desc(cs, qs, bb[r], ord);
+    lr->nbig.push_back((int64_t)(ord.size() - r0));
+    if (r < sb.size()) append_desc(cs, qs, sb[r], ord);
+    lr->bounds.push_back((int64_t)ord.size());
+    for (size_t i = r0; i < ord.size(); ++i) {
+      lid[ord[i]] = (int32_t)r;
+      pos[ord[i]] = (int32_t)i;
+      uoff.push_back(uoff.back() + cs[ord[i]]);
+    }
+    ub_max = std::max(ub_max, uoff.back() - uoff[r0]);
+  }
   lr->pool_elems = std::max<int64_t>(pool_max, 1024);
+  lr->arena_elems = std::max<int64_t>(arena, 1024);
   lr->ub_elems = std::max<int64_t>(ub_max, 1);
-  lr->uoff.alloc(st, (nG + 1) * sizeof(int64_t));
-  HIP_OK(hipMemcpyAsync(lr->uoff.p, uoff.data(), (nG + 1) * sizeof(int64_t),
+  upload_i32(ctx, lr->order, ord);
+  upload_i32(ctx, lr->lid, lid);
+  upload_i32(ctx, lr->pos, pos);
+  lr->uoff.alloc(st, uoff.size() * sizeof(int64_t));
+  HIP_OK(hipMemcpyAsync(lr->uoff.p, uoff.data(), uoff.size() * sizeof(int64_t),
                         hipMemcpyHostToDevice, st));
   ctx_sync(ctx);
 }

@@ -141,22 +141,25 @@ __global__ __launch_bounds__(T256) void k_combine(
   U[3 * o + 2] = (TO)u2;
 }
 
-// Streamed mode: add the rows of the admissible blocks [b0, b1) that contain
-// particle s, walking from its leaf to the root (fixed order, no atomics).
+// Streamed mode: add the rows of the admissible blocks of launch r that
+// contain particle s, walking from its leaf to the root (fixed order, no
+// atomics). Block b's rows sit at uoff[pos[b]] - uoff[start of launch r].
 __global__ __launch_bounds__(T256) void k_far_gather(
     int64_t n, const int32_t* __restrict__ leaf_of, const int32_t* __restrict__ parent,
-    const int4* __restrict__ nodes, const int32_t* __restrict__ far_ptr, int64_t b0, int64_t b1,
+    const int4* __restrict__ nodes, const int32_t* __restrict__ far_ptr, int32_t r,
+    int64_t r0, const int32_t* __restrict__ lid, const int32_t* __restrict__ pos,
     const int64_t* __restrict__ uoff, const double* __restrict__ ublk, double* __restrict__ Uf) {
   int64_t s = (int64_t)blockIdx.x * T256 + threadIdx.x;
   if (s >= n) return;
   double u0 = 0, u1 = 0, u2 = 0;
-  const int64_t base = uoff[b0];
+  const int64_t base = uoff[r0];
   for (int tau = leaf_of[s]; tau >= 0; tau = parent[tau]) {
-    int64_t p0 = max((int64_t)far_ptr[tau], b0), p1 = min((int64_t)far_ptr[tau + 1], b1);
+    const int p0 = far_ptr[tau], p1 = far_ptr[tau + 1];
     if (p0 >= p1) continue;
     const int64_t il = s - nodes[tau].x;
-    for (int64_t p = p0; p < p1; ++p) {
-      const double* u = ublk + 3 * (uoff[p] - base + il);
+    for (int p = p0; p < p1; ++p) {
+      if (lid[p] != r) continue;
+      const double* u = ublk + 3 * (uoff[pos[p]] - base + il);
       u0 += u[0]; u1 += u[1]; u2 += u[2];
     }
   }
@@ -258,8 +261,9 @@ void matvec_streamed_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kerne
     PhaseTimer timer(ctx, HH_PHASE_FAR);
     hipLaunchKernelGGL(k_far_gather, dim3(nblk(n)), dim3(T256), 0, st, n,
                        t->leaf_of.as<int32_t>(), t->parent.as<int32_t>(), t->nodes.as<int4>(),
-                       p->far_ptr.as<int32_t>(), lr->bounds[i], lr->bounds[i + 1],
-                       lr->uoff.as<int64_t>(), lr->ublk.as<double>(), Uf.as<double>());
+                       p->far_ptr.as<int32_t>(), (int32_t)i, lr->bounds[i], lr->lid.as<int32_t>(),
+                       lr->pos.as<int32_t>(), lr->uoff.as<int64_t>(), lr->ublk.as<double>(),
+                       Uf.as<double>());
     HIP_OK(hipGetLastError());
   }
   {

@@ -169,9 +169,12 @@ struct hh_lowrank_s {
   bool stats_dirty = true;
   hh_kernel kern = nullptr;
   int64_t est_elems = 0;
-  std::vector<int64_t> bounds;   // batch block boundaries
-  int64_t ub_elems = 0;          // largest batch sum of c
-  DevBuf uoff;                   // int64 [nG+1] prefix sums of c
+  std::vector<int64_t> bounds;   // launch ranges of the work order
+  int64_t ub_elems = 0;          // largest launch sum of c
+  DevBuf uoff;                   // int64 [nG+1] prefix sums of c over the work order
+  DevBuf lid, pos;               // int32 [nG] launch and work-order position of block b
+  DevBuf arena;                  // per-wave factor arenas of the small blocks
+  int64_t arena_elems = 0, arena_workers = 0;
   DevBuf ublk;                   // double [ub_elems][3]
   DevBuf order;                  // int32 [nG] ACA work order (largest blocks first)
   std::vector<int64_t> nbig;     // per launch range: blocks for whole workgroups
