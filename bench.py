@@ -110,11 +110,17 @@ def cpu_baseline(X, F, kern_cfg, U_gpu, budget_s):
     else:
         ko = OK.Kernel("mlp", OK.MLP(*wl.mlp_weights(1)))
     n = X.shape[0]
+    off = kern_cfg.get("offsets")
     rows = wl.sample_rows(n, 256, seed=3)
     got, t0 = [], time.perf_counter()
     ref = []
     for r in rows:
-        ref.append(OD.dense_u(X, F, ko, np.array([r]))[0])
+        if off is None:
+            ref.append(OD.dense_u(X, F, ko, np.array([r]))[0])
+        else:   # the dense sum over the row's own system
+            s = int(np.searchsorted(off, r, side="right") - 1)
+            a, b = int(off[s]), int(off[s + 1])
+            ref.append(OD.dense_u(X[a:b], F[a:b], ko, np.array([r - a]))[0])
         got.append(r)
         if time.perf_counter() - t0 > budget_s and len(got) >= 4:
             break
@@ -122,9 +128,12 @@ def cpu_baseline(X, F, kern_cfg, U_gpu, budget_s):
     ref = np.array(ref)
     g = np.asarray(got)
     err = float(np.linalg.norm(U_gpu[g] - ref) / np.linalg.norm(ref))
-    return {"value": len(g) / dt, "unit": "particles/s", "cores": int(threads), "kind": "oracle",
-            "sample": "%d sampled rows (seed 3) of the dense FP64 sum over all %d sources, "
-                      "%.1f s" % (len(g), n, dt)}, err, len(g)
+    return ({"value": len(g) / dt, "unit": "particles/s", "cores": int(threads), "kind": "oracle",
+            "sample": ("%d sampled rows (seed 3) of the dense FP64 sum over all %d sources, "
+                       "%.1f s" % (len(g), n, dt)) if off is None else
+                      ("%d sampled rows (seed 3) of the dense FP64 sum over each row's own "
+                       "system (%d systems, %d particles), %.1f s" % (len(g), len(off) - 1, n, dt))},
+            err, len(g))
 
 
 def main():
@@ -155,8 +164,13 @@ def main():
     Fd = torch.tensor(F, dtype=fdt, device="cuda:0")
     torch.cuda.synchronize()
 
+    offsets = cfg.get("offsets")
+
     def step():
-        t = hh.build_tree(ctx, Xd, cfg["c_leaf"])
+        if offsets is None:
+            t = hh.build_tree(ctx, Xd, cfg["c_leaf"])
+        else:
+            t = hh.build_tree_batch(ctx, Xd, offsets, cfg["c_leaf"])
         p = hh.partition(ctx, t, cfg["eta"])
         lr = hh.aca_build(ctx, t, p, kern, prec, cfg["eps"], a.l_max)
         U = hh.matvec(ctx, t, p, lr, kern, Fd, prec)
@@ -194,7 +208,7 @@ def main():
     per_query = MLP_FLOP if cfg["kernel"] == "mlp" else 40
     flop_launch = queries * per_query / launches
     achieved = flop_launch / (launch_ms * 1e-3) / 1e12
-    if prec == "bf16":
+    if prec.startswith("bf16"):
         bound, peak = "mfma", PEAK["bf16_TFs"]
     elif prec == "fp32":
         bound, peak = "alu", PEAK["fp32_TFs"]
@@ -219,11 +233,12 @@ def main():
         "value": n / (ms * 1e-3), "unit": "particles/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32",
-                                                         "bf16": "bf16"}[prec],
+                                                         "bf16": "bf16", "bf16_split": "bf16"}[prec],
         "data": "synthetic",
         "config": {"workload": a.workload, "n": n, "kernel": cfg["kernel"], "precision": prec,
                    "c_leaf": cfg["c_leaf"], "eta": cfg["eta"], "eps": cfg["eps"],
-                   "l_max": a.l_max, "geometry": cfg["geom"], "phi": cfg["phi"]},
+                   "l_max": a.l_max, "geometry": cfg["geom"], "phi": cfg["phi"],
+                   "systems": 1 if offsets is None else len(offsets) - 1},
         "phases_ms": {k: round(v, 3) for k, v in per_step.items()},
         "work": {"nodes": nn, "leaves": nl, "blocks_G": nG, "blocks_H": nH,
                  "near_pairs": pairs_near, "aca_samples": li["samples"],

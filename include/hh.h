@@ -65,8 +65,12 @@ typedef enum {
  *   HH_FP32 : F, U, kernel evaluation, factors and sums in FP32.
  *   HH_BF16 : seeded-MLP layers in BF16 on MFMA with FP32 accumulation; ACA
  *             pivot selection and stopping norms in FP64; factors FP32; the
- *             final velocity sum in FP64. F is FP32 and U is FP64. */
-typedef enum { HH_FP64 = 0, HH_FP32 = 1, HH_BF16 = 2 } hh_precision;
+ *             final velocity sum in FP64. F is FP32 and U is FP64. The ACA
+ *             samples carry the activations as BF16 hi + lo; the near field
+ *             rounds them to BF16 once (about 1e-4 relative per entry).
+ *   HH_BF16_SPLIT : as HH_BF16, with hi + lo activations in the near field
+ *             too (about 1e-6 per entry, about 1.5x the near-field work). */
+typedef enum { HH_FP64 = 0, HH_FP32 = 1, HH_BF16 = 2, HH_BF16_SPLIT = 3 } hh_precision;
 
 /* Input of the seeded MLP kernel: the unit direction r/|r| (default; gives
  * an asymptotically smooth kernel, the premise of the low-rank step at the

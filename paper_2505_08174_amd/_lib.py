@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libhh.so")
 HH_OK = 0
 STATUS = {0: "HH_OK", 1: "HH_ERR_INVALID_ARG", 2: "HH_ERR_OUT_OF_MEMORY", 3: "HH_ERR_HIP",
           4: "HH_ERR_DUPLICATE_POINTS", 5: "HH_ERR_CAPACITY", 6: "HH_ERR_NOT_CONVERGED"}
-HH_FP64, HH_FP32, HH_BF16 = 0, 1, 2
+HH_FP64, HH_FP32, HH_BF16, HH_BF16_SPLIT = 0, 1, 2, 3
 HH_MLP_INPUT_DIRECTION, HH_MLP_INPUT_DISPLACEMENT = 0, 1
 HH_MLP_NPARAM = 9161
 LMAX_CAP = 64

@@ -9,9 +9,12 @@ import torch
 
 from . import _lib as L
 
-PRECISION = {"fp64": L.HH_FP64, "fp32": L.HH_FP32, "bf16": L.HH_BF16}
-F_DTYPE = {L.HH_FP64: torch.float64, L.HH_FP32: torch.float32, L.HH_BF16: torch.float32}
-U_DTYPE = {L.HH_FP64: torch.float64, L.HH_FP32: torch.float32, L.HH_BF16: torch.float64}
+PRECISION = {"fp64": L.HH_FP64, "fp32": L.HH_FP32, "bf16": L.HH_BF16,
+             "bf16_split": L.HH_BF16_SPLIT}
+F_DTYPE = {L.HH_FP64: torch.float64, L.HH_FP32: torch.float32, L.HH_BF16: torch.float32,
+           L.HH_BF16_SPLIT: torch.float32}
+U_DTYPE = {L.HH_FP64: torch.float64, L.HH_FP32: torch.float32, L.HH_BF16: torch.float64,
+           L.HH_BF16_SPLIT: torch.float64}
 
 
 def _prec(p):

@@ -23,6 +23,9 @@
 // Samples, residuals and factors are in the working type T; pivots, norms
 // and Gram matrices in FP64 in every form. In the BF16 form the samples come
 // from the MFMA MLP tile (activations carried as BF16 hi + lo).
+#include <algorithm>
+#include <iterator>
+
 #include "devmath.h"
 #include "internal.h"
 #include "mlp_mfma.h"
@@ -50,13 +53,18 @@ struct AcaArgs {
   int64_t* fptr;     // [nG][LMAX_CAP]
   T* pool;
   int64_t pool_elems;
-  T* arena;             // per-wave factor arenas (streamed mode, single-wave blocks)
-  int64_t arena_elems;  // elements per arena
+  T* arena;             // per-wave factor arenas (streamed mode)
+  int64_t arena_elems;  // elements per wave arena; a workgroup team owns AW of them
+  T* huge;              // arenas of the workgroups that take the huge blocks
+  int64_t huge_elems;   // elements per huge arena
+  int n_huge_wg;        // workgroups blockIdx < n_huge_wg take huge blocks first
   unsigned long long* pool_top;
   int* overflow;
   int* work;         // dynamic block counter (blocks worked on by single waves)
   int* work_big;     // dynamic block counter (blocks worked on by whole workgroups)
-  int64_t nbig;      // order[b0 .. b0 + nbig) go to whole workgroups
+  int* work_huge;    // dynamic block counter (huge blocks, streamed mode)
+  int64_t nhuge;     // order[b0 .. b0 + nhuge) are huge (streamed mode)
+  int64_t nbig;      // then order[.. + nbig) go to whole workgroups
   int64_t b0, b1;    // block range of this launch
   // fused apply (streamed mode): Fs != nullptr
   const T* Fs;       // sorted forces
@@ -291,7 +299,8 @@ __device__ __forceinline__ void team_combine(TeamRed* tr, double* gx, int wit, i
 template <class T, int KIND, bool MF, int TW>
 __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, const bf16x8* fr,
                                            TeamSh<T>& sh, TeamRed* tr, int wit, int64_t slot,
-                                           int* counter, int64_t r0, int64_t r1) {
+                                           int* counter, int64_t r0, int64_t r1, T* fbase,
+                                           int64_t fcap) {
   using NT = double;
   const int lane = threadIdx.x & 63;
   const bool lead = wit == 0 && lane == 0;
@@ -299,10 +308,6 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
   const int tid = 64 * wit + lane;
   double* hA = a.gram + slot * a.gram_stride;
   double* gx = hA + a.gram_half;   // cross-wave partials, [AW][64][9]
-  // factor storage: a wave's own arena (offsets restart with every block) or
-  // the shared pool (bump-allocated)
-  const bool own = TW == 1 && a.arena != nullptr;
-  T* const fb = own ? a.arena + slot * a.arena_elems : a.pool;
 #pragma unroll 1
   for (;;) {
     if (lead) sh.bo = atomicAdd(counter, 1);
@@ -317,6 +322,10 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
     const double* xt = a.xs + 3 * (int64_t)nt.x;
     const double* xsr = a.xs + 3 * (int64_t)ns.x;
     const int kmax = min(min(c, q), a.l_max);
+    // factor storage: the worker's own arena (fcap elements; offsets restart
+    // with every block), or the shared pool, bump-allocated (fbase == null)
+    const bool own = fbase != nullptr;
+    T* const fb = own ? fbase : a.pool;
     int j = q / 2;
     int rank = 0;
     bool converged = false, fallback = false, pending = false;
@@ -336,7 +345,7 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
         int ovf = 0;
         if (own) {
           o = (unsigned long long)k * need;
-          ovf = (int64_t)(o + need) > a.arena_elems;
+          ovf = (int64_t)(o + need) > fcap;
         } else {
           o = atomicAdd(a.pool_top, need);
           ovf = (int64_t)(o + need) > a.pool_elems;
@@ -754,9 +763,10 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
   }
 }
 
-// Workgroups of AW waves: first the whole workgroup works as one team on the
-// large blocks order[b0 .. b0 + nbig) (largest first), then every wave works
-// alone on the rest.
+// Workgroups of AW waves. Streamed mode: the first n_huge_wg workgroups start
+// on the huge blocks order[b0 .. b0 + nhuge), each in its own large arena.
+// Then every workgroup works as one team on the large blocks (next nbig in
+// the order, largest first), then every wave works alone on the rest.
 template <class T, int KIND, bool MF>
 __global__ __launch_bounds__(AW_T) void k_aca(AcaArgs<T> a) {
   __shared__ T wl[(KIND == KIND_MLP && !MF) ? MLP_NP : 1];
@@ -771,19 +781,28 @@ __global__ __launch_bounds__(AW_T) void k_aca(AcaArgs<T> a) {
   }
   __syncthreads();
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
-  if (a.nbig > 0)
-    aca_worker<T, KIND, MF, AW>(a, wl, fr, shw[0], &tr, wv, (int64_t)blockIdx.x * AW,
-                                a.work_big, a.b0, a.b0 + a.nbig);
+  const int64_t wg = blockIdx.x;
+  const bool ar = a.arena != nullptr;   // streamed mode: arenas, else the shared pool
+  const int64_t r1 = a.b0 + a.nhuge, r2 = r1 + a.nbig;
+  if (a.nhuge > 0 && wg < a.n_huge_wg)
+    aca_worker<T, KIND, MF, AW>(a, wl, fr, shw[0], &tr, wv, wg * AW, a.work_huge, a.b0, r1,
+                                a.huge + wg * a.huge_elems, a.huge_elems);
   __syncthreads();
-  aca_worker<T, KIND, MF, 1>(a, wl, fr, shw[wv], &tr, 0, (int64_t)blockIdx.x * AW + wv, a.work,
-                             a.b0 + a.nbig, a.b1);
+  if (a.nbig > 0)
+    aca_worker<T, KIND, MF, AW>(a, wl, fr, shw[0], &tr, wv, wg * AW, a.work_big, r1, r2,
+                                ar ? a.arena + wg * AW * a.arena_elems : nullptr,
+                                AW * a.arena_elems);
+  __syncthreads();
+  aca_worker<T, KIND, MF, 1>(a, wl, fr, shw[wv], &tr, 0, wg * AW + wv, a.work, r2, a.b1,
+                             ar ? a.arena + (wg * AW + wv) * a.arena_elems : nullptr,
+                             a.arena_elems);
 }
 
 template <class T>
 void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
                   int64_t b0, int64_t b1, T* pool, int64_t pool_elems, void* pool_top,
-                  int* overflow, int* work, int* work_big, int64_t nbig, const void* Fs,
-                  double* ublk, const int64_t* uoff) {
+                  int* overflow, int* work, int* work_big, int* work_huge, int64_t nbig,
+                  int64_t nhuge, const void* Fs, double* ublk, const int64_t* uoff) {
   AcaArgs<T> a;
   a.G = p->G.as<int2>();
   a.nG = p->nG;
@@ -809,7 +828,9 @@ void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
   a.overflow = overflow;
   a.work = work;
   a.work_big = work_big;
+  a.work_huge = work_huge;
   a.nbig = nbig;
+  a.nhuge = nhuge;
   a.b0 = b0;
   a.b1 = b1;
   a.Fs = (const T*)Fs;
@@ -820,7 +841,7 @@ void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
   const int64_t nb = b1 - b0;
   if (nb <= 0) return;
   // persistent grid: as many workgroups as stay resident, each wave a worker
-  const void* fn = (k->kind == KIND_MLP && lr->prec == HH_BF16)
+  const void* fn = (k->kind == KIND_MLP && is_bf16(lr->prec))
                        ? (const void*)k_aca<float, KIND_MLP, true>
                        : (k->kind == KIND_MLP ? (const void*)k_aca<T, KIND_MLP, false>
                                               : (const void*)k_aca<T, KIND_RPY, false>);
@@ -828,7 +849,7 @@ void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
   HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, AW_T, 0));
   HH_REQUIRE(per_cu > 0, HH_ERR_HIP, "ACA kernel does not fit a compute unit");
   int64_t grid = (int64_t)per_cu * ctx->n_cu;
-  grid = std::min<int64_t>(grid, std::max<int64_t>(nbig, (nb + AW - 1) / AW));
+  grid = std::min<int64_t>(grid, std::max(std::max(nbig, nhuge), (nb + AW - 1) / AW));
   // per worker: Gram history A (l_max (l_max + 1) / 2 3x3 matrices), then the
   // cross-wave partials of a workgroup team [AW][64][9]
   const int64_t half = 9 * ((int64_t)lr->l_max * (lr->l_max + 1) / 2);
@@ -844,17 +865,34 @@ void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
   a.gram_half = half;
   a.arena = nullptr;
   a.arena_elems = 0;
-  if (Fs && lr->arena_elems > 0) {
+  a.huge = nullptr;
+  a.huge_elems = 0;
+  a.n_huge_wg = 0;
+  if (Fs) {
+    // streamed mode: a factor arena per wave; huge blocks go to the first
+    // n_huge_wg workgroups, as many arenas of huge_elems as half the budget holds
     if (lr->arena_workers < workers) {
       lr->arena.alloc(ctx->stream, workers * lr->arena_elems * sizeof(T));
       lr->arena_workers = workers;
     }
     a.arena = lr->arena.as<T>();
     a.arena_elems = lr->arena_elems;
+    if (nhuge > 0) {
+      const int64_t fit = (int64_t)(0.5 * (double)ctx->budget_bytes /
+                                    ((double)lr->huge_elems * sizeof(T)));
+      const int64_t nh = std::max<int64_t>(1, std::min(grid, fit));
+      if (lr->huge_wg < nh) {
+        lr->huge.alloc(ctx->stream, nh * lr->huge_elems * sizeof(T));
+        lr->huge_wg = nh;
+      }
+      a.huge = lr->huge.as<T>();
+      a.huge_elems = lr->huge_elems;
+      a.n_huge_wg = (int)nh;
+    }
   }
 #define LAUNCH(KIND_, MF_)                                                                  \
   hipLaunchKernelGGL((k_aca<T, KIND_, MF_>), dim3((unsigned)grid), dim3(AW_T), 0, ctx->stream, a)
-  if (k->kind == KIND_MLP && lr->prec == HH_BF16) {
+  if (k->kind == KIND_MLP && is_bf16(lr->prec)) {
     if constexpr (sizeof(T) == 4) LAUNCH(KIND_MLP, true);
   } else if (k->kind == KIND_MLP) {
     LAUNCH(KIND_MLP, false);
@@ -957,17 +995,17 @@ static void upload_i32(hh_ctx ctx, DevBuf& d, const std::vector<int32_t>& v) {
                           ctx->stream));
 }
 
-// Plans the ACA. Each launch works on a range of the work order: first the
-// large blocks (c + q >= 2^team_cls, whole workgroups, largest first), then
-// the small ones (single waves, largest first).
+// Plans the ACA. Each launch works on a range of the work order: the large
+// blocks (c + q >= 2^team_cls, whole workgroups, largest first), then the
+// small ones (single waves, largest first).
 // Stored mode: one launch over all blocks; the factors stay in the pool.
-// Streamed mode (factors would not fit the context budget; Sec. 3.3.2: a
-// fixed buffer is filled by a group of blocks, applied, then reused): the
-// large blocks go in batches whose worst-case factor storage fits half the
-// budget (bump-allocated in a shared pool); a small block only lives while
-// its wave works on it, so it takes a fixed per-wave arena and the small
-// blocks are split only by the size of their output rows. Launch r takes
-// large batch r and small chunk r.
+// Streamed mode (the factors would not fit half the context budget; Sec.
+// 3.3.2: a fixed buffer is filled by a group of blocks, applied, then
+// reused): a block's factors only live while its worker approximates it, so
+// every wave has a fixed factor arena (sized for the worst case of the small
+// blocks), a workgroup team uses the arenas of its waves, and the huge blocks
+// whose worst case exceeds that go first to a few workgroups with large
+// arenas. Launches are split only by the size of their output rows.
 void plan_aca(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, int force_streamed) {
   hipStream_t st = ctx->stream;
   int64_t nG = p->nG;
@@ -1004,61 +1042,62 @@ void plan_aca(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, int force_streame
     append_desc(cs, qs, small, ord);
     lr->bounds.push_back(nG);
     lr->nbig.push_back((int64_t)big.size());
+    lr->nhuge.assign(1, 0);
     lr->arena_elems = 0;
     upload_i32(ctx, lr->order, ord);
     ctx_sync(ctx);
     return;
   }
-  // large blocks: batches by worst-case factor storage
-  const double cap = 0.5 * (double)ctx->budget_bytes;
-  std::vector<std::vector<int32_t>> bb(1), sb(1);
-  double acc = 0;
-  int64_t pe = 0, pool_max = 0;
+  // streamed: small blocks in a per-wave arena, large ones in the arenas of a
+  // workgroup's waves, huge ones (worst case above that) in a few large
+  // arenas; launches are split only by the size of their output rows
+  const int64_t wave_arena = std::max<int64_t>(arena, 1024);
+  const int64_t team_arena = (int64_t)AW * wave_arena;
+  std::vector<char> kind(std::max<int64_t>(nG, 1), 0);   // 0 small, 1 large, 2 huge
+  int64_t huge_max = 0;
   for (int32_t b : big) {
     const int64_t cq = (int64_t)cs[b] + qs[b];
     const int64_t kc = std::min<int64_t>(std::min(cs[b], qs[b]), lr->l_max);
-    const double bytes = (double)(9 * cq * kc) * es + 24.0 * cs[b];
-    if (acc > 0 && acc + bytes > cap) {
-      bb.emplace_back();
-      pool_max = std::max(pool_max, pe);
-      acc = 0;
-      pe = 0;
-    }
-    bb.back().push_back(b);
-    acc += bytes;
-    pe += 9 * cq * kc;
+    const int64_t w = 9 * cq * kc;
+    kind[b] = w > team_arena ? 2 : 1;
+    if (w > team_arena) huge_max = std::max(huge_max, w);
   }
-  pool_max = std::max(pool_max, pe);
-  // small blocks: chunks by output rows (24 bytes per row)
   const int64_t rows_cap = std::max<int64_t>(1, (int64_t)(0.2 * (double)ctx->budget_bytes / 24.0));
-  int64_t rows = 0;
-  for (int32_t b : small) {
-    if (rows > 0 && rows + cs[b] > rows_cap) {
-      sb.emplace_back();
-      rows = 0;
-    }
-    sb.back().push_back(b);
-    rows += cs[b];
-  }
-  const size_t L = std::max(bb.size(), sb.size());
   std::vector<int32_t> lid(std::max<int64_t>(nG, 1)), pos(std::max<int64_t>(nG, 1));
   std::vector<int64_t> uoff(1, 0);
   int64_t ub_max = 0;
-  for (size_t r = 0; r < L; ++r) {
+  lr->nhuge.clear();
+  std::vector<int32_t> hb, tb, wb;
+  int64_t rows = 0;
+  auto close = [&]() {
     const size_t r0 = ord.size();
-    if (r < bb.size()) append_desc(cs, qs, bb[r], ord);
-    lr->nbig.push_back((int64_t)(ord.size() - r0));
-    if (r < sb.size()) append_desc(cs, qs, sb[r], ord);
+    const int32_t r = (int32_t)lr->nbig.size();
+    append_desc(cs, qs, hb, ord);
+    lr->nhuge.push_back((int64_t)hb.size());
+    append_desc(cs, qs, tb, ord);
+    lr->nbig.push_back((int64_t)tb.size());
+    append_desc(cs, qs, wb, ord);
     lr->bounds.push_back((int64_t)ord.size());
     for (size_t i = r0; i < ord.size(); ++i) {
-      lid[ord[i]] = (int32_t)r;
+      lid[ord[i]] = r;
       pos[ord[i]] = (int32_t)i;
       uoff.push_back(uoff.back() + cs[ord[i]]);
     }
     ub_max = std::max(ub_max, uoff.back() - uoff[r0]);
+    hb.clear();
+    tb.clear();
+    wb.clear();
+    rows = 0;
+  };
+  for (int64_t b = 0; b < nG; ++b) {
+    if (rows > 0 && rows + cs[b] > rows_cap) close();
+    (kind[b] == 2 ? hb : kind[b] == 1 ? tb : wb).push_back((int32_t)b);
+    rows += cs[b];
   }
-  lr->pool_elems = std::max<int64_t>(pool_max, 1024);
-  lr->arena_elems = std::max<int64_t>(arena, 1024);
+  if (rows > 0 || lr->nbig.empty()) close();
+  lr->arena_elems = wave_arena;
+  lr->huge_elems = std::max<int64_t>(huge_max, 1024);
+  lr->pool_elems = 1024;   // the shared pool is not used in streamed mode
   lr->ub_elems = std::max<int64_t>(ub_max, 1);
   upload_i32(ctx, lr->order, ord);
   upload_i32(ctx, lr->lid, lid);
@@ -1086,10 +1125,12 @@ void run_aca_stored(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr
       PhaseTimer timer(ctx, HH_PHASE_ACA);
       if (lr->prec == HH_FP64)
         launch_aca_t<double>(ctx, t, p, k, lr, 0, nG, lr->pool.as<double>(), lr->pool_elems, top,
-                             flags, flags + 1, flags + 2, lr->nbig[0], nullptr, nullptr, nullptr);
+                             flags, flags + 1, flags + 2, flags + 3, lr->nbig[0], 0, nullptr,
+                             nullptr, nullptr);
       else
         launch_aca_t<float>(ctx, t, p, k, lr, 0, nG, lr->pool.as<float>(), lr->pool_elems, top,
-                            flags, flags + 1, flags + 2, lr->nbig[0], nullptr, nullptr, nullptr);
+                            flags, flags + 1, flags + 2, flags + 3, lr->nbig[0], 0, nullptr,
+                            nullptr, nullptr);
     }
     HIP_OK(hipMemcpyAsync(ctx->pinned, ctx->scratch_flag.p, 8 * sizeof(int64_t),
                           hipMemcpyDeviceToHost, st));
@@ -1107,20 +1148,20 @@ void run_aca_stored(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr
   lr->tbuf.alloc(st, std::max<int64_t>(1, lr->rank_sum) * 3 * sizeof(double));
 }
 
-// Streamed mode, batch i: ACA with the apply fused in; per-block rows go to
-// ublk (offsets uoff - uoff[b0]). counters: 2 int64 per batch, zeroed.
+// Streamed mode, launch i: ACA with the apply fused in; per-block rows go to
+// ublk (offsets uoff[pos] - uoff[b0]). counters: 4 int64 per launch, zeroed.
 void run_aca_batch(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr, size_t i,
                    const void* Fs, int64_t* counters) {
   int64_t b0 = lr->bounds[i], b1 = lr->bounds[i + 1];
-  int* work = (int*)(counters + 2 * i);   // [0] single waves, [1] workgroups
-  int64_t* top = counters + 2 * i + 1;
+  int* work = (int*)(counters + 4 * i);   // single waves, workgroups, huge blocks
+  int64_t* top = counters + 4 * i + 2;
   int* ovf = (int*)ctx->scratch_flag.p;
   if (lr->prec == HH_FP64)
     launch_aca_t<double>(ctx, t, p, k, lr, b0, b1, lr->pool.as<double>(), lr->pool_elems, top,
-                         ovf, work, work + 1, lr->nbig[i], Fs, lr->ublk.as<double>(),
-                         lr->uoff.as<int64_t>());
+                         ovf, work, work + 1, work + 2, lr->nbig[i], lr->nhuge[i], Fs,
+                         lr->ublk.as<double>(), lr->uoff.as<int64_t>());
   else
     launch_aca_t<float>(ctx, t, p, k, lr, b0, b1, lr->pool.as<float>(), lr->pool_elems, top, ovf,
-                        work, work + 1, lr->nbig[i], Fs, lr->ublk.as<double>(),
-                        lr->uoff.as<int64_t>());
+                        work, work + 1, work + 2, lr->nbig[i], lr->nhuge[i], Fs,
+                        lr->ublk.as<double>(), lr->uoff.as<int64_t>());
 }

@@ -249,8 +249,8 @@ void matvec_streamed_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kerne
   }
   HIP_OK(hipMemsetAsync(Uf.p, 0, 3 * n * sizeof(double), st));
   const size_t nb = lr->bounds.size() - 1;
-  counters.alloc(st, 2 * nb * sizeof(int64_t));
-  HIP_OK(hipMemsetAsync(counters.p, 0, 2 * nb * sizeof(int64_t), st));
+  counters.alloc(st, 4 * nb * sizeof(int64_t));
+  HIP_OK(hipMemsetAsync(counters.p, 0, 4 * nb * sizeof(int64_t), st));
   if (!lr->pool.p) lr->pool.alloc(st, lr->pool_elems * (lr->prec == HH_FP64 ? 8 : 4));
   if (!lr->ublk.p) lr->ublk.alloc(st, lr->ub_elems * 3 * sizeof(double));
   for (size_t i = 0; i < nb; ++i) {
@@ -286,7 +286,7 @@ hh_status hh_aca_build(hh_ctx ctx, hh_tree tree, hh_part part, hh_kernel kern,
   HH_API_BEGIN(ctx)
   HH_REQUIRE(out && tree && part && kern, HH_ERR_INVALID_ARG, "NULL argument");
   HH_REQUIRE(part->tree == tree, HH_ERR_INVALID_ARG, "partition was built on another tree");
-  HH_REQUIRE(prec == HH_FP64 || prec == HH_FP32 || prec == HH_BF16, HH_ERR_INVALID_ARG,
+  HH_REQUIRE(prec == HH_FP64 || prec == HH_FP32 || is_bf16(prec), HH_ERR_INVALID_ARG,
              "unknown precision");
   HH_REQUIRE(eps >= 0.0 && eps < INFINITY, HH_ERR_INVALID_ARG, "eps must be >= 0");
   HH_REQUIRE(l_max >= 1 && l_max <= LMAX_CAP, HH_ERR_INVALID_ARG, "l_max must be in [1, 64]");
@@ -318,7 +318,7 @@ hh_status hh_matvec(hh_ctx ctx, hh_tree tree, hh_part part, hh_lowrank lr, hh_ke
   HH_REQUIRE(lr->prec == prec, HH_ERR_INVALID_ARG, "precision differs from the ACA build");
   HH_REQUIRE(lr->kern == kern, HH_ERR_INVALID_ARG, "kernel differs from the ACA build");
   // <storage/kernel type, F type, U type, near-field row type>
-  const bool mfma = prec == HH_BF16 && kern->kind == KIND_MLP;
+  const bool mfma = is_bf16(prec) && kern->kind == KIND_MLP;
   if (lr->streamed) {
     if (prec == HH_FP64)
       matvec_streamed_t<double, double, double, double>(ctx, tree, part, lr, kern, F, U);

@@ -173,11 +173,14 @@ struct hh_lowrank_s {
   int64_t ub_elems = 0;          // largest launch sum of c
   DevBuf uoff;                   // int64 [nG+1] prefix sums of c over the work order
   DevBuf lid, pos;               // int32 [nG] launch and work-order position of block b
-  DevBuf arena;                  // per-wave factor arenas of the small blocks
+  DevBuf arena;                  // per-wave factor arenas (streamed mode)
   int64_t arena_elems = 0, arena_workers = 0;
+  DevBuf huge;                   // arenas of the workgroups taking huge blocks
+  int64_t huge_elems = 0, huge_wg = 0;
   DevBuf ublk;                   // double [ub_elems][3]
   DevBuf order;                  // int32 [nG] ACA work order (largest blocks first)
   std::vector<int64_t> nbig;     // per launch range: blocks for whole workgroups
+  std::vector<int64_t> nhuge;    // per launch range: huge blocks (streamed mode)
   // Gram history of the block being approximated, one slot per ACA worker
   DevBuf gram;
   int64_t gram_workers = 0, gram_stride = 0;
@@ -186,6 +189,7 @@ struct hh_lowrank_s {
 // ------------------------------------------------------------- helpers
 
 size_t elem_size(int prec);
+inline bool is_bf16(int prec) { return prec == HH_BF16 || prec == HH_BF16_SPLIT; }
 void ctx_sync(hh_ctx ctx);
 int64_t read_i64(hh_ctx ctx, const void* dev_ptr);
 void read_bytes(hh_ctx ctx, void* host, const void* dev, size_t bytes);
@@ -199,7 +203,8 @@ void radix_sort_u64(hh_ctx ctx, uint64_t* keys, uint32_t* vals, int64_t n, int b
 // Near-field, ACA, far-field and combine launches (near.hip, aca.hip, apply.hip).
 void launch_near(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, int prec, const void* F,
                  void* Unear);
-void launch_near_bf16(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void* Fs, void* Un);
+void launch_near_bf16(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void* Fs, void* Un,
+                      bool split);
 void ensure_units(hh_ctx ctx, hh_tree t);
 void launch_near_neg(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, int prec, const void* Vs,
                      void* out);

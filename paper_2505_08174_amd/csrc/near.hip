@@ -127,5 +127,5 @@ void launch_near(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, int prec, const 
   else if (prec == HH_FP32 || k->kind != KIND_MLP)
     launch_near_t<float>(ctx, t, p, k, Fs, Un);
   else
-    launch_near_bf16(ctx, t, p, k, Fs, Un);      // writes FP64 rows
+    launch_near_bf16(ctx, t, p, k, Fs, Un, prec == HH_BF16_SPLIT);   // writes FP64 rows
 }

@@ -48,6 +48,7 @@ struct NearB {
   int input_mode;
 };
 
+template <bool ACC>
 __global__ __launch_bounds__(NB_T) void k_near_bf16(NearB a) {
   __shared__ bf16x8 fr[FR_TOTAL];
   stage_frags(fr, a.frags, NB_T);
@@ -77,9 +78,9 @@ __global__ __launch_bounds__(NB_T) void k_near_bf16(NearB a) {
       const float rs = hh_rsqrt(rx * rx + ry * ry + rz * rz);
       float o[9];
       if (dir)
-        mlp_tile_bf16<false>(fr, rx * rs, ry * rs, rz * rs, o);
+        mlp_tile_bf16<ACC>(fr, rx * rs, ry * rs, rz * rs, o);
       else
-        mlp_tile_bf16<false>(fr, rx, ry, rz, o);
+        mlp_tile_bf16<ACC>(fr, rx, ry, rz, o);
       const float sc = skip ? 0.0f : rs * c16;
       const float f0 = a.Fs[3 * (int64_t)j], f1 = a.Fs[3 * (int64_t)j + 1],
                   f2 = a.Fs[3 * (int64_t)j + 2];
@@ -117,7 +118,8 @@ void ensure_units(hh_ctx ctx, hh_tree t) {
   t->n_units = nu;
 }
 
-void launch_near_bf16(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void* Fs, void* Un) {
+void launch_near_bf16(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void* Fs, void* Un,
+                      bool split) {
   HH_REQUIRE(k->kind == KIND_MLP, HH_ERR_INVALID_ARG, "the BF16 form needs the MLP kernel");
   ensure_units(ctx, t);
   NearB a;
@@ -133,6 +135,9 @@ void launch_near_bf16(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void*
   a.Un = (double*)Un;
   a.input_mode = k->input_mode;
   unsigned grid = (unsigned)((t->n_units + 3) / 4);
-  hipLaunchKernelGGL(k_near_bf16, dim3(grid), dim3(NB_T), 0, ctx->stream, a);
+  if (split)
+    hipLaunchKernelGGL(k_near_bf16<true>, dim3(grid), dim3(NB_T), 0, ctx->stream, a);
+  else
+    hipLaunchKernelGGL(k_near_bf16<false>, dim3(grid), dim3(NB_T), 0, ctx->stream, a);
   HIP_OK(hipGetLastError());
 }

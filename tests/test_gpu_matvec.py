@@ -240,3 +240,43 @@ def test_workgroup_teams_match_single_waves(kind, prec, eps, tol):
     assert _rel(U2, U1) < 10 * eps
     assert _rel(U3, U1) < 10 * eps
     assert _rel(U2[rows], Ud) <= tol and _rel(U3[rows], Ud) <= tol
+
+
+def test_bf16_split_dense_mode():
+    """Near field with hi + lo BF16 activations: per-entry error ~1e-6, far
+    below the once-rounded BF16 near field."""
+    from gpu_common import ctx, dev, kernels, say
+    n = 3000
+    X = wl.rsa_cube(n, 0.2, seed=2)
+    F = wl.normal_forces(n, seed=2)
+    ko, kg = kernels("mlp")
+    rows = wl.sample_rows(n, 400, seed=3)
+    Ud = OD.dense_u(X, F, ko, rows)
+    errs = {}
+    for prec in ("bf16", "bf16_split"):
+        hm = hh.HMatrix(ctx(), dev(X), kg, c_leaf=64, prec=prec, dense_mode=True)
+        U = (hm @ dev(F, torch.float32)).cpu().numpy()
+        errs[prec] = _rel(U[rows], Ud)
+    say("dense mode, random forces", errs)
+    assert errs["bf16_split"] <= 5e-5
+    assert errs["bf16_split"] < errs["bf16"]
+
+
+def test_bf16_split_as_accurate_as_fp32():
+    """With zero-mean random forces (no coherent flow to hide the kernel
+    error) the split BF16 form reaches the plain FP32 form's accuracy."""
+    from gpu_common import ctx, dev, kernels, say
+    n = 8000
+    X = wl.rsa_cube(n, 0.2, seed=6)
+    F = wl.normal_forces(n, seed=6)
+    ko, kg = kernels("mlp")
+    rows = wl.sample_rows(n, 300, seed=3)
+    Ud = OD.dense_u(X, F, ko, rows)
+    errs = {}
+    for prec in ("fp32", "bf16_split", "bf16"):
+        hm = hh.HMatrix(ctx(), dev(X), kg, c_leaf=64, eta=1.0, eps=1e-4, prec=prec)
+        U = (hm @ dev(F, torch.float32)).double().cpu().numpy()
+        errs[prec] = _rel(U[rows], Ud)
+    say("eps_r by form", errs)
+    assert errs["bf16_split"] <= max(2 * errs["fp32"], 1e-4)
+    assert errs["bf16"] <= 5e-3

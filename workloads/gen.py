@@ -312,12 +312,21 @@ WORKLOADS = {
                       kernel="mlp", precision="fp32", c_leaf=128, eta=1.0, eps=1e-4),
     "diff_5k": dict(n=5000, geom="cube", phi=0.15, seed=0, forces="normal",
                     kernel="mlp", precision="fp32", c_leaf=128, eta=1.0, eps=1e-4),
+    # 64 independent systems (batch_workload): n is the total, set when generated
+    "batch64": dict(n=None, geom="batch", phi=None, seed=2, forces="normal",
+                    kernel="mlp", precision="bf16", c_leaf=128, eta=1.0, eps=1e-4),
 }
 
 
 def workload(name: str, n: int | None = None):
     """Positions and forces of a named workload (optionally at another n)."""
     w = dict(WORKLOADS[name])
+    if w["geom"] == "batch":
+        X, F, off, specs = batch_workload(seed=w["seed"])
+        w["n"] = int(X.shape[0])
+        w["offsets"] = off
+        w["systems"] = specs
+        return X, F, w
     if n is not None:
         w["n"] = int(n)
     if w["geom"] == "cube":
