@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--l-max", type=int, default=48)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick leaf sizes (per size class of systems) and the workgroup "
+                         "threshold by timing whole steps first (not timed)")
     return ap.parse_args()
 
 
@@ -165,12 +168,34 @@ def main():
     torch.cuda.synchronize()
 
     offsets = cfg.get("offsets")
+    c_leaf = cfg["c_leaf"]
+    tuned = None
+    if a.autotune:
+        from paper_2505_08174_amd import autotune as AT
+        t0 = time.perf_counter()
+        if offsets is None:
+            best, times = AT.tune_leaf(ctx, Xd, Fd, kern, prec, cfg["eps"], cfg["eta"])
+            team = {}
+            for tm in AT.TEAM_CANDIDATES:
+                ctx.set_team_min(tm)
+                team[tm] = AT._time_step(ctx, Xd, Fd, kern, prec, cfg["eps"], cfg["eta"], best)
+            ctx.set_team_min(min(team, key=team.get))
+            c_leaf = best
+            tuned = {"c_leaf": best, "team_min": min(team, key=team.get)}
+        else:
+            kinds = [sp["kind"] for sp in cfg["systems"]]
+            r = AT.tune_batch(ctx, Xd, Fd, offsets, kern, prec, cfg["eps"], cfg["eta"], kinds)
+            c_leaf = r["c_leafs"]
+            tuned = {"c_leafs": np.bincount(r["c_leafs"]).nonzero()[0].tolist(),
+                     "c_leaf_per_system": r["c_leafs"].tolist(), "team_min": r["team_min"]}
+        tuned["seconds"] = round(time.perf_counter() - t0, 1)
+        log("autotuned:", tuned)
 
     def step():
         if offsets is None:
-            t = hh.build_tree(ctx, Xd, cfg["c_leaf"])
+            t = hh.build_tree(ctx, Xd, c_leaf)
         else:
-            t = hh.build_tree_batch(ctx, Xd, offsets, cfg["c_leaf"])
+            t = hh.build_tree_batch(ctx, Xd, offsets, c_leaf)
         p = hh.partition(ctx, t, cfg["eta"])
         lr = hh.aca_build(ctx, t, p, kern, prec, cfg["eps"], a.l_max)
         U = hh.matvec(ctx, t, p, lr, kern, Fd, prec)
@@ -236,7 +261,8 @@ def main():
                                                          "bf16": "bf16", "bf16_split": "bf16"}[prec],
         "data": "synthetic",
         "config": {"workload": a.workload, "n": n, "kernel": cfg["kernel"], "precision": prec,
-                   "c_leaf": cfg["c_leaf"], "eta": cfg["eta"], "eps": cfg["eps"],
+                   "c_leaf": cfg["c_leaf"] if tuned is None else tuned,
+                   "eta": cfg["eta"], "eps": cfg["eps"],
                    "l_max": a.l_max, "geometry": cfg["geom"], "phi": cfg["phi"],
                    "systems": 1 if offsets is None else len(offsets) - 1},
         "phases_ms": {k: round(v, 3) for k, v in per_step.items()},

@@ -143,6 +143,11 @@ hh_status hh_build_tree(hh_ctx ctx, const double* X, int64_t n, int32_t c_leaf, 
  * plus an empty system -> HH_ERR_INVALID_ARG. Syncs. */
 hh_status hh_build_tree_batch(hh_ctx ctx, const double* X, const int64_t* offsets,
                               int32_t n_sys, int32_t c_leaf, hh_tree* out);
+/* As hh_build_tree_batch with a leaf size per system: c_leafs is a host
+ * array of n_sys values, each >= 2 (system s is the tree hh_build_tree would
+ * build on it with c_leafs[s]). NULL c_leafs -> HH_ERR_INVALID_ARG. Syncs. */
+hh_status hh_build_tree_batch_leaf(hh_ctx ctx, const double* X, const int64_t* offsets,
+                                   int32_t n_sys, const int32_t* c_leafs, hh_tree* out);
 
 /* Block partition (Algorithm 1) with the admissibility test Eq. (7) on tight
  * bounding boxes of the member centres: admissible iff dist^2 > 0 and

@@ -37,6 +37,8 @@ SIGNATURES = {
     "hh_kernel_free": (None, [_vp]),
     "hh_build_tree": (C.c_int, [_vp, _vp, _i64, _i32, C.POINTER(_vp)]),
     "hh_build_tree_batch": (C.c_int, [_vp, _vp, _pi64, _i32, _i32, C.POINTER(_vp)]),
+    "hh_build_tree_batch_leaf": (C.c_int, [_vp, _vp, _pi64, _i32, C.POINTER(_i32),
+                                           C.POINTER(_vp)]),
     "hh_partition": (C.c_int, [_vp, _vp, _d, C.c_int, C.POINTER(_vp)]),
     "hh_aca_build": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int, _d, _i32, C.POINTER(_vp)]),
     "hh_matvec": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int, _vp, _vp]),

@@ -206,15 +206,24 @@ def build_tree(ctx: Context, X: torch.Tensor, c_leaf: int) -> Tree:
     return Tree(ctx, h)
 
 
-def build_tree_batch(ctx: Context, X: torch.Tensor, offsets, c_leaf: int) -> Tree:
-    """One tree over several independent systems (concatenated in X)."""
+def build_tree_batch(ctx: Context, X: torch.Tensor, offsets, c_leaf) -> Tree:
+    """One tree over several independent systems (concatenated in X); c_leaf
+    is one leaf size or one per system."""
     assert X.is_cuda and X.dtype == torch.float64 and X.dim() == 2 and X.shape[1] == 3
     X = X.contiguous()
     off = np.ascontiguousarray(offsets, dtype=np.int64)
     assert off[0] == 0 and off[-1] == X.shape[0]
     h = C.c_void_p()
-    ctx.check(L.load().hh_build_tree_batch(ctx.h, _ptr(X), off.ctypes.data_as(C.POINTER(C.c_int64)),
-                                           len(off) - 1, int(c_leaf), C.byref(h)))
+    p64 = off.ctypes.data_as(C.POINTER(C.c_int64))
+    if np.ndim(c_leaf) == 0:
+        ctx.check(L.load().hh_build_tree_batch(ctx.h, _ptr(X), p64, len(off) - 1, int(c_leaf),
+                                               C.byref(h)))
+    else:
+        cl = np.ascontiguousarray(c_leaf, dtype=np.int32)
+        assert cl.shape == (len(off) - 1,)
+        ctx.check(L.load().hh_build_tree_batch_leaf(ctx.h, _ptr(X), p64, len(off) - 1,
+                                                    cl.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                    C.byref(h)))
     return Tree(ctx, h)
 
 
@@ -318,6 +327,30 @@ class HMatrix:
 
     def __matmul__(self, F):
         return matvec(self.ctx, self.tree, self.part, self.lr, self.kern, F, self.prec)
+
+    def capture(self, F: torch.Tensor):
+        """Record the product U = M F in a hipGraph (a torch.cuda.CUDAGraph).
+
+        One eager product runs first (it sizes every workspace, so the
+        recorded launches allocate nothing); replaying the graph recomputes U
+        (returned) from the current contents of F. In streamed mode the graph
+        holds the whole ACA with the fused apply. F and U must keep their
+        storage while the graph is in use; products on one H-matrix must not
+        overlap in time. Returns (graph, U)."""
+        assert F.is_contiguous()
+        U = torch.empty(F.shape, dtype=U_DTYPE[self.prec], device=F.device)
+        matvec(self.ctx, self.tree, self.part, self.lr, self.kern, F, self.prec, U)
+        torch.cuda.synchronize(F.device)
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream(F.device)
+        home = torch.cuda.current_stream(F.device)
+        try:
+            with torch.cuda.graph(g, stream=side):
+                self.ctx.set_stream(side)
+                matvec(self.ctx, self.tree, self.part, self.lr, self.kern, F, self.prec, U)
+        finally:
+            self.ctx.set_stream(home)
+        return g, U
 
 
 def hmatvec(ctx, X, F, kern, c_leaf=64, eta=1.0, eps=1e-6, prec="fp64", l_max=48):

@@ -198,9 +198,10 @@ void matvec_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kernel k, cons
               void* U) {
   hipStream_t st = ctx->stream;
   const int64_t n = t->n;
-  DevBuf Fs, Un;
-  Fs.alloc(st, 3 * n * sizeof(T));
-  Un.alloc(st, 3 * n * sizeof(TU));
+  DevBuf& Fs = lr->ws_f;
+  DevBuf& Un = lr->ws_near;
+  Fs.ensure(st, 3 * n * sizeof(T));
+  Un.ensure(st, 3 * n * sizeof(TU));
   hipLaunchKernelGGL((k_gather_rows<TI, T>), dim3(nblk(n)), dim3(T256), 0, st, (const TI*)F,
                      t->perm.as<int32_t>(), n, Fs.as<T>());
   {
@@ -237,20 +238,23 @@ void matvec_streamed_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kerne
                        const void* F, void* U) {
   hipStream_t st = ctx->stream;
   const int64_t n = t->n;
-  DevBuf Fs, Un, Uf, counters;
-  Fs.alloc(st, 3 * n * sizeof(T));
-  Un.alloc(st, 3 * n * sizeof(TU));
-  Uf.alloc(st, 3 * n * sizeof(double));
+  DevBuf& Fs = lr->ws_f;
+  DevBuf& Un = lr->ws_near;
+  DevBuf& Uf = lr->ws_far;
+  DevBuf& counters = lr->ws_cnt;
+  Fs.ensure(st, 3 * n * sizeof(T));
+  Un.ensure(st, 3 * n * sizeof(TU));
+  Uf.ensure(st, 3 * n * sizeof(double));
   hipLaunchKernelGGL((k_gather_rows<TI, T>), dim3(nblk(n)), dim3(T256), 0, st, (const TI*)F,
                      t->perm.as<int32_t>(), n, Fs.as<T>());
   {
     PhaseTimer timer(ctx, HH_PHASE_NEAR);
     launch_near(ctx, t, p, k, lr->prec, Fs.p, Un.p);
   }
-  HIP_OK(hipMemsetAsync(Uf.p, 0, 3 * n * sizeof(double), st));
+  zero_words(ctx, Uf.p, 3 * n);
   const size_t nb = lr->bounds.size() - 1;
-  counters.alloc(st, 4 * nb * sizeof(int64_t));
-  HIP_OK(hipMemsetAsync(counters.p, 0, 4 * nb * sizeof(int64_t), st));
+  counters.ensure(st, 4 * nb * sizeof(int64_t));
+  zero_words(ctx, counters.p, 4 * (int64_t)nb);
   if (!lr->pool.p) lr->pool.alloc(st, lr->pool_elems * (lr->prec == HH_FP64 ? 8 : 4));
   if (!lr->ublk.p) lr->ublk.alloc(st, lr->ub_elems * 3 * sizeof(double));
   for (size_t i = 0; i < nb; ++i) {

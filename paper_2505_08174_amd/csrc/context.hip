@@ -42,6 +42,9 @@ static hipEvent_t take_event(hh_ctx ctx) {
 
 PhaseTimer::PhaseTimer(hh_ctx c, int ph) : ctx(c), phase(ph) {
   if (!ctx->profiling) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(ctx->stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+    return;   // no timing events inside a captured graph
   a = take_event(ctx);
   (void)hipEventRecord(a, ctx->stream);
 }
@@ -75,6 +78,20 @@ static void drain_phases(hh_ctx ctx) {
 }
 
 size_t elem_size(int prec) { return prec == HH_FP64 ? 8 : 4; }
+
+namespace {
+__global__ void k_zero_words(int64_t* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    p[i] = 0;
+}
+}  // namespace
+
+void zero_words(hh_ctx ctx, void* p, int64_t n) {
+  if (n <= 0) return;
+  const int64_t g = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_zero_words, dim3((unsigned)g), dim3(256), 0, ctx->stream, (int64_t*)p, n);
+  HIP_OK(hipGetLastError());
+}
 
 void ctx_sync(hh_ctx ctx) { HIP_OK(hipStreamSynchronize(ctx->stream)); }
 

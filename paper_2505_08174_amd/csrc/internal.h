@@ -44,6 +44,11 @@ struct DevBuf {
   ~DevBuf() { release(); }
   void release();
   void alloc(hipStream_t stream, size_t nbytes);
+  // keeps the buffer when it already holds nbytes (no allocation, so a
+  // repeated call can be captured in a graph)
+  void ensure(hipStream_t stream, size_t nbytes) {
+    if (!p || bytes < nbytes) alloc(stream, nbytes);
+  }
   template <class T> T* as() const { return reinterpret_cast<T*>(p); }
 };
 
@@ -111,7 +116,8 @@ static_assert(MLP_NP == HH_MLP_NPARAM, "packed MLP layout");
 struct hh_tree_s {
   hh_ctx ctx = nullptr;
   int64_t n = 0;
-  int32_t c_leaf = 0;
+  int32_t c_leaf = 0;            // largest leaf size over the systems
+  DevBuf cl;                     // int32 [n_sys] leaf size of every system
   int64_t n_nodes = 0, n_leaves = 0;
   DevBuf perm;      // int32 [n]   input index at sorted position
   DevBuf keys;      // uint64 [n]  sorted Morton keys
@@ -181,6 +187,9 @@ struct hh_lowrank_s {
   DevBuf order;                  // int32 [nG] ACA work order (largest blocks first)
   std::vector<int64_t> nbig;     // per launch range: blocks for whole workgroups
   std::vector<int64_t> nhuge;    // per launch range: huge blocks (streamed mode)
+  // product workspaces, kept between products (sorted F, near rows, far rows,
+  // work counters)
+  DevBuf ws_f, ws_near, ws_far, ws_cnt;
   // Gram history of the block being approximated, one slot per ACA worker
   DevBuf gram;
   int64_t gram_workers = 0, gram_stride = 0;
@@ -191,6 +200,9 @@ struct hh_lowrank_s {
 size_t elem_size(int prec);
 inline bool is_bf16(int prec) { return prec == HH_BF16 || prec == HH_BF16_SPLIT; }
 void ctx_sync(hh_ctx ctx);
+// Zeroes n 64-bit words on the stream with a kernel (no memset node, so it
+// can sit in a captured graph).
+void zero_words(hh_ctx ctx, void* p, int64_t n);
 int64_t read_i64(hh_ctx ctx, const void* dev_ptr);
 void read_bytes(hh_ctx ctx, void* host, const void* dev, size_t bytes);
 

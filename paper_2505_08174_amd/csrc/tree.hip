@@ -11,6 +11,8 @@
 // midpoint bisection of the cube with empty halves skipped.
 #include <math.h>
 
+#include <algorithm>
+
 #include "api_guard.h"
 #include "internal.h"
 
@@ -245,13 +247,14 @@ __device__ __forceinline__ bool mixed(const int2* __restrict__ rng, const int32_
   return sy[r.x] != sy[r.y];
 }
 
+// cl: leaf size C_leaf of every system
 __device__ __forceinline__ bool splittable(const int2* __restrict__ rng,
                                            const uint64_t* __restrict__ k,
                                            const int32_t* __restrict__ sy, int64_t n, int u,
-                                           int c_leaf) {
+                                           const int32_t* __restrict__ cl) {
   if (u >= n - 1) return false;
   int2 r = rng[u];
-  return sy[r.x] == sy[r.y] && (r.y - r.x + 1) >= c_leaf && k[r.x] != k[r.y];
+  return sy[r.x] == sy[r.y] && (r.y - r.x + 1) >= cl[sy[r.x]] && k[r.x] != k[r.y];
 }
 
 // kept: a system root (no parent, or a parent spanning systems) or a son of
@@ -260,13 +263,14 @@ __global__ __launch_bounds__(T256) void k_keep(const int2* __restrict__ rng,
                                                const int32_t* __restrict__ par,
                                                const uint64_t* __restrict__ k,
                                                const int32_t* __restrict__ sy, int64_t n,
-                                               int c_leaf, int64_t* __restrict__ flag) {
+                                               const int32_t* __restrict__ cl,
+                                               int64_t* __restrict__ flag) {
   int64_t u = (int64_t)blockIdx.x * T256 + threadIdx.x;
   if (u >= 2 * n - 1) return;
   bool kept;
   if (mixed(rng, sy, n, (int)u)) kept = false;
   else if (par[u] < 0 || mixed(rng, sy, n, par[u])) kept = true;
-  else kept = splittable(rng, k, sy, n, par[u], c_leaf);
+  else kept = splittable(rng, k, sy, n, par[u], cl);
   flag[u] = kept ? 1 : 0;
 }
 
@@ -294,7 +298,8 @@ __global__ __launch_bounds__(T256) void k_nodes(const uint32_t* __restrict__ sva
                                                 const int2* __restrict__ kid,
                                                 const uint64_t* __restrict__ k,
                                                 const int32_t* __restrict__ sy, int64_t n,
-                                                int c_leaf, const int32_t* __restrict__ map,
+                                                const int32_t* __restrict__ cl,
+                                                const int32_t* __restrict__ map,
                                                 int4* __restrict__ nodes,
                                                 int32_t* __restrict__ parent,
                                                 int64_t* __restrict__ isleaf) {
@@ -303,7 +308,7 @@ __global__ __launch_bounds__(T256) void k_nodes(const uint32_t* __restrict__ sva
   int u = (int)sval[p];
   int2 r = node_range(rng, n, u);
   int4 nd = make_int4(r.x, r.y + 1, -1, -1);
-  if (splittable(rng, k, sy, n, u, c_leaf)) {
+  if (splittable(rng, k, sy, n, u, cl)) {
     int2 c = kid[u];
     nd.z = map[c.x];
     nd.w = map[c.y];
@@ -418,14 +423,16 @@ inline unsigned nblk(int64_t n, int t = T256) { return (unsigned)((n + t - 1) / 
 }  // namespace
 
 static void build_tree_impl(hh_ctx ctx, hh_tree_s* t, const double* X, int64_t n,
-                            const std::vector<int64_t>& offs, int32_t c_leaf) {
+                            const std::vector<int64_t>& offs, const std::vector<int32_t>& cls) {
   hipStream_t st = ctx->stream;
   const int nsys = (int)offs.size() - 1;
   int sbits = 0;
   while ((1 << sbits) < nsys) ++sbits;
   t->ctx = ctx;
   t->n = n;
-  t->c_leaf = c_leaf;
+  t->c_leaf = *std::max_element(cls.begin(), cls.end());
+  t->cl.alloc(st, nsys * sizeof(int32_t));
+  HIP_OK(hipMemcpyAsync(t->cl.p, cls.data(), nsys * sizeof(int32_t), hipMemcpyHostToDevice, st));
   t->n_sys = nsys;
   t->offs_host = offs;
   t->offs.alloc(st, (nsys + 1) * sizeof(int64_t));
@@ -482,8 +489,8 @@ static void build_tree_impl(hh_ctx ctx, hh_tree_s* t, const double* X, int64_t n
   kpos.alloc(st, (nt + 1) * sizeof(int64_t));
   HIP_OK(hipMemsetAsync(keep.as<int64_t>() + nt, 0, sizeof(int64_t), st));
   hipLaunchKernelGGL(k_keep, dim3(nblk(nt)), dim3(T256), 0, st, rng.as<int2>(),
-                     par.as<int32_t>(), t->keys.as<uint64_t>(), sysk.as<int32_t>(), n, c_leaf,
-                     keep.as<int64_t>());
+                     par.as<int32_t>(), t->keys.as<uint64_t>(), sysk.as<int32_t>(), n,
+                     t->cl.as<int32_t>(), keep.as<int64_t>());
   scan_exclusive_i64(ctx, keep.as<int64_t>(), kpos.as<int64_t>(), nt + 1);
   HIP_OK(hipMemcpyAsync(ctx->pinned, kpos.as<int64_t>() + nt, 8, hipMemcpyDeviceToHost, st));
   HIP_OK(hipMemcpyAsync(ctx->pinned + 1, flags, 8, hipMemcpyDeviceToHost, st));
@@ -514,7 +521,8 @@ static void build_tree_impl(hh_ctx ctx, hh_tree_s* t, const double* X, int64_t n
   HIP_OK(hipMemsetAsync(isleaf.as<int64_t>() + m, 0, sizeof(int64_t), st));
   hipLaunchKernelGGL(k_nodes, dim3(nblk(m)), dim3(T256), 0, st, sval.as<uint32_t>(), m,
                      rng.as<int2>(), kid.as<int2>(), t->keys.as<uint64_t>(), sysk.as<int32_t>(),
-                     n, c_leaf, map.as<int32_t>(), t->nodes.as<int4>(), t->parent.as<int32_t>(),
+                     n, t->cl.as<int32_t>(), map.as<int32_t>(), t->nodes.as<int4>(),
+                     t->parent.as<int32_t>(),
                      isleaf.as<int64_t>());
   t->roots.alloc(st, nsys * sizeof(int32_t));
   hipLaunchKernelGGL(k_roots, dim3(nblk(m)), dim3(T256), 0, st, t->nodes.as<int4>(), m,
@@ -547,7 +555,35 @@ hh_status hh_build_tree(hh_ctx ctx, const double* X, int64_t n, int32_t c_leaf, 
   PhaseTimer timer(ctx, HH_PHASE_TREE);
   hh_tree_s* t = new hh_tree_s();
   try {
-    build_tree_impl(ctx, t, X, n, std::vector<int64_t>{0, n}, c_leaf);
+    build_tree_impl(ctx, t, X, n, std::vector<int64_t>{0, n}, std::vector<int32_t>{c_leaf});
+  } catch (...) {
+    delete t;
+    throw;
+  }
+  *out = t;
+  HH_API_END(ctx)
+}
+
+static hh_status build_batch(hh_ctx ctx, const double* X, const int64_t* offsets, int32_t n_sys,
+                             const int32_t* c_leafs, int32_t c_leaf, hh_tree* out) {
+  if (out) *out = nullptr;
+  HH_API_BEGIN(ctx)
+  HH_REQUIRE(out && X && offsets, HH_ERR_INVALID_ARG, "NULL argument");
+  HH_REQUIRE(n_sys >= 1 && n_sys <= (1 << 20), HH_ERR_INVALID_ARG, "n_sys must be in [1, 2^20]");
+  std::vector<int32_t> cls(n_sys, c_leaf);
+  if (c_leafs) cls.assign(c_leafs, c_leafs + n_sys);
+  for (int s = 0; s < n_sys; ++s)
+    HH_REQUIRE(cls[s] >= 2, HH_ERR_INVALID_ARG, "c_leaf must be >= 2");
+  std::vector<int64_t> offs(offsets, offsets + n_sys + 1);
+  HH_REQUIRE(offs[0] == 0, HH_ERR_INVALID_ARG, "offsets[0] must be 0");
+  for (int s = 0; s < n_sys; ++s)
+    HH_REQUIRE(offs[s + 1] > offs[s], HH_ERR_INVALID_ARG, "every system needs >= 1 particle");
+  const int64_t n = offs[n_sys];
+  HH_REQUIRE(n < (1ll << 31) - 1, HH_ERR_INVALID_ARG, "total n must be < 2^31-1");
+  PhaseTimer timer(ctx, HH_PHASE_TREE);
+  hh_tree_s* t = new hh_tree_s();
+  try {
+    build_tree_impl(ctx, t, X, n, offs, cls);
   } catch (...) {
     delete t;
     throw;
@@ -558,27 +594,17 @@ hh_status hh_build_tree(hh_ctx ctx, const double* X, int64_t n, int32_t c_leaf, 
 
 hh_status hh_build_tree_batch(hh_ctx ctx, const double* X, const int64_t* offsets, int32_t n_sys,
                               int32_t c_leaf, hh_tree* out) {
-  if (out) *out = nullptr;
-  HH_API_BEGIN(ctx)
-  HH_REQUIRE(out && X && offsets, HH_ERR_INVALID_ARG, "NULL argument");
-  HH_REQUIRE(n_sys >= 1 && n_sys <= (1 << 20), HH_ERR_INVALID_ARG, "n_sys must be in [1, 2^20]");
-  HH_REQUIRE(c_leaf >= 2, HH_ERR_INVALID_ARG, "c_leaf must be >= 2");
-  std::vector<int64_t> offs(offsets, offsets + n_sys + 1);
-  HH_REQUIRE(offs[0] == 0, HH_ERR_INVALID_ARG, "offsets[0] must be 0");
-  for (int s = 0; s < n_sys; ++s)
-    HH_REQUIRE(offs[s + 1] > offs[s], HH_ERR_INVALID_ARG, "every system needs >= 1 particle");
-  const int64_t n = offs[n_sys];
-  HH_REQUIRE(n < (1ll << 31) - 1, HH_ERR_INVALID_ARG, "total n must be < 2^31-1");
-  PhaseTimer timer(ctx, HH_PHASE_TREE);
-  hh_tree_s* t = new hh_tree_s();
-  try {
-    build_tree_impl(ctx, t, X, n, offs, c_leaf);
-  } catch (...) {
-    delete t;
-    throw;
+  return build_batch(ctx, X, offsets, n_sys, nullptr, c_leaf, out);
+}
+
+hh_status hh_build_tree_batch_leaf(hh_ctx ctx, const double* X, const int64_t* offsets,
+                                   int32_t n_sys, const int32_t* c_leafs, hh_tree* out) {
+  if (!c_leafs) {
+    if (out) *out = nullptr;
+    if (ctx) ctx->last_error = "NULL argument";
+    return HH_ERR_INVALID_ARG;
   }
-  *out = t;
-  HH_API_END(ctx)
+  return build_batch(ctx, X, offsets, n_sys, c_leafs, 2, out);
 }
 
 void hh_tree_free(hh_tree t) { delete t; }

@@ -72,6 +72,37 @@ def test_batched_tree_and_partition_equal_per_system_oracle(c_leaf):
     assert np.array_equal(g, G) and np.array_equal(h, H)
 
 
+def test_per_system_leaf_sizes_equal_per_system_oracle():
+    """Each system with its own C_leaf: its subtree and blocks are the
+    oracle's single-system ones built with that leaf size."""
+    from gpu_common import ctx, dev, say
+    cls = [16, 64, 2, 32, 128, 8, 48, 100]
+    say("per-system leaf sizes", cls)
+    Xs, X, off = _systems(SIZES)
+    t = hh.build_tree_batch(ctx(), dev(X), off, np.array(cls))
+    ex = t.export()
+    g, h = hh.partition(ctx(), t, 1.0).export()
+    node0 = 0
+    Gs, Hs, nodes = [], [], []
+    for s, Xk in enumerate(Xs):
+        ref = OT.build_tree(Xk, cls[s])
+        a = off[s]
+        assert np.array_equal(ex["perm"][a:off[s + 1]], ref.perm + a), s
+        nd = ref.nodes.copy()
+        nd[:, :2] += a
+        nd[:, 2:] = np.where(nd[:, 2:] >= 0, nd[:, 2:] + node0, -1)
+        nodes.append(nd)
+        G, H = OP.build_partition(ref, 1.0)
+        Gs.append(G + node0)
+        Hs.append(H + node0)
+        node0 += ref.nodes.shape[0]
+    assert np.array_equal(ex["nodes"], np.concatenate(nodes))
+    assert np.array_equal(g, np.concatenate(Gs).reshape(-1, 2))
+    assert np.array_equal(h, np.concatenate(Hs).reshape(-1, 2))
+    with pytest.raises(hh.HHError):
+        hh.build_tree_batch(ctx(), dev(X), off, np.array([1] + cls[1:]))
+
+
 def test_batched_tree_rejects_bad_offsets():
     from gpu_common import ctx, dev, say
     say("batched tree errors")
