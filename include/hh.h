@@ -62,7 +62,8 @@ typedef enum {
 
 /* Arithmetic of the kernel evaluation, factors and sums.
  *   HH_FP64 : F, U, factors and all sums in FP64.
- *   HH_FP32 : F, U, kernel evaluation, factors and sums in FP32.
+ *   HH_FP32 : F, U, kernel evaluation and factors in FP32; ACA pivots and
+ *             stopping norms in FP64 (as in every form).
  *   HH_BF16 : seeded-MLP layers in BF16 on MFMA with FP32 accumulation; ACA
  *             pivot selection and stopping norms in FP64; factors FP32; the
  *             final velocity sum in FP64. F is FP32 and U is FP64. The ACA
@@ -158,12 +159,16 @@ hh_status hh_partition(hh_ctx ctx, hh_tree tree, double eta, int dense_mode, hh_
 
 /* Adaptive cross approximation (Algorithm 2, Eqs. (8)-(10)) of every
  * admissible block, with 3x3 entries: first column j_1 = floor(q/2), row and
- * column pivots by largest squared Frobenius norm of the residual entry (ties
- * to the lowest index), c_k normalised by the inverse of its pivot entry,
- * stop when nu^2 <= eps^2 lambda^2 (exact block norms through 3x3 Gram
- * matrices) or when min(c, q) terms interpolate the block. A block that
- * reaches l_max terms without converging is evaluated densely by hh_matvec
- * (counted in hh_lowrank_info). eps >= 0, 1 <= l_max <= 64. Syncs. */
+ * column pivots by the largest magnitude of the residual entry (squared
+ * Frobenius norm in HH_FP64, |det| in the single-precision forms; ties to
+ * the lowest index), c_k normalised by the inverse of its pivot entry, stop
+ * when nu^2 <= eps^2 lambda^2 (exact block norms through 3x3 Gram matrices)
+ * or when min(c, q) terms interpolate the block. A block that reaches l_max
+ * terms without converging is evaluated densely (counted in
+ * hh_lowrank_info). eps >= 0, 1 <= l_max <= 64. Syncs.
+ * When the factors would not fit half the context budget the handle is in
+ * streamed mode: this call only plans, and hh_matvec runs the ACA with the
+ * product fused in and keeps no factors (Sec. 3.3.2). */
 hh_status hh_aca_build(hh_ctx ctx, hh_tree tree, hh_part part, hh_kernel kern,
                        hh_precision prec, double eps, int32_t l_max, hh_lowrank* out);
 
@@ -171,7 +176,10 @@ hh_status hh_aca_build(hh_ctx ctx, hh_tree tree, hh_part part, hh_kernel kern,
  * terms). F: device [n][3] (FP64 for HH_FP64, FP32 otherwise). U: device
  * [n][3] (FP32 for HH_FP32, FP64 otherwise), fully overwritten, input order.
  * lr must come from hh_aca_build with the same tree, partition, kernel and
- * precision. Does not sync. */
+ * precision. Does not sync. Workspaces live in lr: the first call sizes
+ * them; later calls allocate nothing and record no memset, so they can be
+ * captured in a HIP graph (with profiling off). Products on one lr must not
+ * overlap in time. */
 hh_status hh_matvec(hh_ctx ctx, hh_tree tree, hh_part part, hh_lowrank lr, hh_kernel kern,
                     hh_precision prec, const void* F, void* U);
 
