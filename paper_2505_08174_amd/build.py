@@ -19,6 +19,8 @@ ARCH = "gfx950"
 FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in VGPRs: no v_accvgpr_read per result register
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I" + os.path.join(os.path.dirname(HERE), "include"),
     "-Wno-unused-result",
 ]

@@ -136,11 +136,17 @@ static int kslot_feature(int s, int h, int u) {
 
 // Fragment table of the BF16 MFMA MLP (layout in mlp_mfma.h): 16 bytes
 // (8 BF16) per lane and fragment.
-static std::vector<uint16_t> build_bf16_frags(const double* P) {
+// Layers 1-3 (those followed by tanh) are stored scaled by 2 log2(e): the
+// tile then takes tanh(x) = 1 - 2 / (2^y + 1) straight from the result y.
+static std::vector<uint16_t> build_bf16_frags(const double* P0) {
   const int L1 = 0, L2 = L1 + 2 * 64, L3 = L2 + (2 * 4 * 2 + 2) * 64,
             L4 = L3 + (2 * 4 * 2 + 2) * 64, TOTAL = L4 + (4 * 2 + 1) * 64;
   std::vector<uint16_t> fr((size_t)TOTAL * 8, 0);
   auto at = [&](int frag, int u) -> uint16_t& { return fr[(size_t)frag * 8 + u]; };
+  const double S = 2.0 / log(2.0);
+  std::vector<double> Ps(P0, P0 + MLP_NP);
+  for (int i = OFF_W1; i < OFF_W4; ++i) Ps[i] *= S;   // W1, b1, W2, b2, W3, b3
+  const double* P = Ps.data();
   const double* W1 = P + OFF_W1;
   const double* b1 = P + OFF_B1;
   for (int mo = 0; mo < 2; ++mo)

@@ -42,14 +42,33 @@ __device__ __forceinline__ f32x16 mfma_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
 }
 
 // tanh of 8 consecutive result registers -> one BF16 B operand (and, for
-// the accurate tile, the BF16 remainder t - hi as a second operand)
+// the accurate tile, the BF16 remainder as a second operand). Layers 1-3 are
+// stored scaled by 2 log2(e), so a result register y holds 2 log2(e) times
+// the pre-activation x and tanh(x) = 1 - 2 / (2^y + 1). The accurate tile
+// adds the remainder t - hi, rounded to BF16. Values go in pairs through one
+// two-way BF16 conversion.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float tanh_scaled(float y) {
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(y) + 1.0f);
+}
+
 template <bool ACC>
 __device__ __forceinline__ void act8(const f32x16& a, int base, bf16x8& hi, bf16x8& lo) {
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    float t = hh_tanh(a[base + u]);
-    hi[u] = (__bf16)t;
-    if (ACC) lo[u] = (__bf16)(t - (float)hi[u]);
+  for (int u = 0; u < 8; u += 2) {
+    const f32x2 t = {tanh_scaled(a[base + u]), tanh_scaled(a[base + u + 1])};
+    const bf16x2 h = __builtin_convertvector(t, bf16x2);
+    hi[u] = h[0];
+    hi[u + 1] = h[1];
+    if (ACC) {
+      const uint32_t hb = __builtin_bit_cast(uint32_t, h);
+      const f32x2 r = {t[0] - __uint_as_float(hb << 16), t[1] - __uint_as_float(hb & 0xffff0000u)};
+      const bf16x2 l = __builtin_convertvector(r, bf16x2);
+      lo[u] = l[0];
+      lo[u + 1] = l[1];
+    }
   }
 }
 
