@@ -84,20 +84,38 @@ __device__ __forceinline__ NT det3(const T* K) {
               (NT)K[2] * ((NT)K[3] * (NT)K[7] - (NT)K[4] * (NT)K[6]));
 }
 
-// K(x_i - y_j) from the MFMA MLP tile: symmetrised 3x3 entry of a pair.
+// K(x_i - y_j) from NT independent MFMA MLP tiles: symmetrised 3x3 entries
+// of this lane's pair of each tile (accurate tiles: hi + lo activations).
+template <int NT>
+__device__ __forceinline__ void mfma_entries(const bf16x8* fr, int mode, const double (&d)[NT][3],
+                                             float (&K)[NT][9]) {
+  float v[NT][3], rs[NT], o[NT][9];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const float rx = (float)d[t][0], ry = (float)d[t][1], rz = (float)d[t][2];
+    rs[t] = hh_rsqrt(rx * rx + ry * ry + rz * rz);
+    const float sc = mode == HH_MLP_INPUT_DIRECTION ? rs[t] : 1.0f;
+    v[t][0] = rx * sc;
+    v[t][1] = ry * sc;
+    v[t][2] = rz * sc;
+  }
+  mlp_tiles_bf16<true, NT>(fr, v, o);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const float s = rs[t] * (float)(1.0 / (16.0 * HH_PI));
+    K[t][0] = 2.0f * o[t][0] * s; K[t][1] = (o[t][1] + o[t][3]) * s; K[t][2] = (o[t][2] + o[t][6]) * s;
+    K[t][3] = K[t][1];            K[t][4] = 2.0f * o[t][4] * s;       K[t][5] = (o[t][5] + o[t][7]) * s;
+    K[t][6] = K[t][2];            K[t][7] = K[t][5];                  K[t][8] = 2.0f * o[t][8] * s;
+  }
+}
+
 __device__ __forceinline__ void mfma_entry(const bf16x8* fr, int mode, double dx, double dy,
                                            double dz, float K[9]) {
-  float rx = (float)dx, ry = (float)dy, rz = (float)dz;
-  const float rs = hh_rsqrt(rx * rx + ry * ry + rz * rz);
-  float o[9];
-  if (mode == HH_MLP_INPUT_DIRECTION)
-    mlp_tile_bf16<true>(fr, rx * rs, ry * rs, rz * rs, o);
-  else
-    mlp_tile_bf16<true>(fr, rx, ry, rz, o);
-  const float s = rs * (float)(1.0 / (16.0 * HH_PI));
-  K[0] = 2.0f * o[0] * s; K[1] = (o[1] + o[3]) * s; K[2] = (o[2] + o[6]) * s;
-  K[3] = K[1];            K[4] = 2.0f * o[4] * s;   K[5] = (o[5] + o[7]) * s;
-  K[6] = K[2];            K[7] = K[5];              K[8] = 2.0f * o[8] * s;
+  const double d[1][3] = {{dx, dy, dz}};
+  float k1[1][9];
+  mfma_entries<1>(fr, mode, d, k1);
+#pragma unroll
+  for (int e = 0; e < 9; ++e) K[e] = k1[0][e];
 }
 
 __device__ __forceinline__ int tri(int m) { return m * (m + 1) / 2; }
@@ -201,28 +219,51 @@ __device__ __forceinline__ void team_sync() {
 // Raw samples K(sgn (p_i - y)) for rows i in [0, n) of `pts`, written to
 // slot[9 i ..]: 32-row MFMA tiles, lanes l and l + 32 share a row, the tiles
 // spread over the TW waves of the team.
+template <int NT>
+__device__ __forceinline__ void sample_tiles(const bf16x8* fr, int mode, const double* pts, int n,
+                                             double y0, double y1, double y2, double sgn,
+                                             float* slot, int t0, int step) {
+  const int lane = threadIdx.x & 63;
+  double d[NT][3];
+  int row[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int tb = t0 + t * step;
+    const int i = tb + (lane & 31);
+    row[t] = i;
+    const int ii = i < n ? i : tb;
+    d[t][0] = sgn * (pts[3 * ii] - y0);
+    d[t][1] = sgn * (pts[3 * ii + 1] - y1);
+    d[t][2] = sgn * (pts[3 * ii + 2] - y2);
+  }
+  float K[NT][9];
+  mfma_entries<NT>(fr, mode, d, K);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int i = row[t];
+    if (i < n) {
+      if (lane < 32) {
+#pragma unroll
+        for (int e = 0; e < 5; ++e) slot[9 * (int64_t)i + e] = K[t][e];
+      } else {
+#pragma unroll
+        for (int e = 5; e < 9; ++e) slot[9 * (int64_t)i + e] = K[t][e];
+      }
+    }
+  }
+}
+
 template <int TW>
 __device__ __forceinline__ void sample_mfma(const bf16x8* fr, int mode, const double* pts, int n,
                                             double y0, double y1, double y2, double sgn,
                                             float* slot, int wit) {
-  const int lane = threadIdx.x & 63;
+  // this wave's tiles t0, t0 + 32 TW, ... in pairs (two independent MFMA chains)
+  const int step = 32 * TW;
+  int t0 = 32 * wit;
 #pragma unroll 1
-  for (int t0 = 32 * wit; t0 < n; t0 += 32 * TW) {
-    const int i = t0 + (lane & 31);
-    const int ii = i < n ? i : t0;
-    float K[9];
-    mfma_entry(fr, mode, sgn * (pts[3 * ii] - y0), sgn * (pts[3 * ii + 1] - y1),
-               sgn * (pts[3 * ii + 2] - y2), K);
-    if (i < n) {
-      if (lane < 32) {
-#pragma unroll
-        for (int e = 0; e < 5; ++e) slot[9 * (int64_t)i + e] = K[e];
-      } else {
-#pragma unroll
-        for (int e = 5; e < 9; ++e) slot[9 * (int64_t)i + e] = K[e];
-      }
-    }
-  }
+  for (; t0 + step < n; t0 += 2 * step)
+    sample_tiles<2>(fr, mode, pts, n, y0, y1, y2, sgn, slot, t0, step);
+  if (t0 < n) sample_tiles<1>(fr, mode, pts, n, y0, y1, y2, sgn, slot, t0, step);
 }
 
 // Combines the per-wave results of a pass over the team: sums v[0..NV) in
@@ -763,15 +804,15 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
   }
 }
 
-// Workgroups of AW waves. Streamed mode: the first n_huge_wg workgroups start
-// on the huge blocks order[b0 .. b0 + nhuge), each in its own large arena.
-// Then every workgroup works as one team on the large blocks (next nbig in
-// the order, largest first), then every wave works alone on the rest.
+// Workgroups of AW waves working as one team per block. Streamed mode: the
+// first n_huge_wg workgroups start on the huge blocks order[b0 .. b0 + nhuge),
+// each in its own large arena. Then every workgroup takes the large blocks
+// (the next nbig in the order, largest first).
 template <class T, int KIND, bool MF>
-__global__ __launch_bounds__(AW_T) void k_aca(AcaArgs<T> a) {
+__global__ __launch_bounds__(AW_T) void k_aca_team(AcaArgs<T> a) {
   __shared__ T wl[(KIND == KIND_MLP && !MF) ? MLP_NP : 1];
   __shared__ bf16x8 fr[MF ? FR_TOTAL : 1];
-  __shared__ TeamSh<T> shw[AW];
+  __shared__ TeamSh<T> sh;
   __shared__ TeamRed tr;
   if (MF) {
     stage_frags(fr, a.frags, AW_T);
@@ -785,15 +826,33 @@ __global__ __launch_bounds__(AW_T) void k_aca(AcaArgs<T> a) {
   const bool ar = a.arena != nullptr;   // streamed mode: arenas, else the shared pool
   const int64_t r1 = a.b0 + a.nhuge, r2 = r1 + a.nbig;
   if (a.nhuge > 0 && wg < a.n_huge_wg)
-    aca_worker<T, KIND, MF, AW>(a, wl, fr, shw[0], &tr, wv, wg * AW, a.work_huge, a.b0, r1,
+    aca_worker<T, KIND, MF, AW>(a, wl, fr, sh, &tr, wv, wg * AW, a.work_huge, a.b0, r1,
                                 a.huge + wg * a.huge_elems, a.huge_elems);
   __syncthreads();
-  if (a.nbig > 0)
-    aca_worker<T, KIND, MF, AW>(a, wl, fr, shw[0], &tr, wv, wg * AW, a.work_big, r1, r2,
-                                ar ? a.arena + wg * AW * a.arena_elems : nullptr,
-                                AW * a.arena_elems);
+  aca_worker<T, KIND, MF, AW>(a, wl, fr, sh, &tr, wv, wg * AW, a.work_big, r1, r2,
+                              ar ? a.arena + wg * AW * a.arena_elems : nullptr,
+                              AW * a.arena_elems);
+}
+
+// Workgroups of AW waves, every wave a worker on its own small blocks
+// order[b0 + nhuge + nbig .. b1) (largest first).
+template <class T, int KIND, bool MF>
+__global__ __launch_bounds__(AW_T) void k_aca(AcaArgs<T> a) {
+  __shared__ T wl[(KIND == KIND_MLP && !MF) ? MLP_NP : 1];
+  __shared__ bf16x8 fr[MF ? FR_TOTAL : 1];
+  __shared__ TeamSh<T> shw[AW];
+  if (MF) {
+    stage_frags(fr, a.frags, AW_T);
+  } else if (KIND == KIND_MLP) {
+    const T* w = (const T*)a.kp.w;
+    for (int i = threadIdx.x; i < MLP_NP; i += AW_T) wl[i] = w[i];
+  }
   __syncthreads();
-  aca_worker<T, KIND, MF, 1>(a, wl, fr, shw[wv], &tr, 0, wg * AW + wv, a.work, r2, a.b1,
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
+  const int64_t wg = blockIdx.x;
+  const bool ar = a.arena != nullptr;
+  aca_worker<T, KIND, MF, 1>(a, wl, fr, shw[wv], nullptr, 0, wg * AW + wv, a.work,
+                             a.b0 + a.nhuge + a.nbig, a.b1,
                              ar ? a.arena + (wg * AW + wv) * a.arena_elems : nullptr,
                              a.arena_elems);
 }
@@ -841,15 +900,23 @@ void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
   const int64_t nb = b1 - b0;
   if (nb <= 0) return;
   // persistent grid: as many workgroups as stay resident, each wave a worker
-  const void* fn = (k->kind == KIND_MLP && is_bf16(lr->prec))
-                       ? (const void*)k_aca<float, KIND_MLP, true>
-                       : (k->kind == KIND_MLP ? (const void*)k_aca<T, KIND_MLP, false>
-                                              : (const void*)k_aca<T, KIND_RPY, false>);
-  int per_cu = 0;
+  const bool mf = k->kind == KIND_MLP && is_bf16(lr->prec);
+  const void* fn = mf ? (const void*)k_aca<float, KIND_MLP, true>
+                      : (k->kind == KIND_MLP ? (const void*)k_aca<T, KIND_MLP, false>
+                                             : (const void*)k_aca<T, KIND_RPY, false>);
+  const void* fnt = mf ? (const void*)k_aca_team<float, KIND_MLP, true>
+                       : (k->kind == KIND_MLP ? (const void*)k_aca_team<T, KIND_MLP, false>
+                                              : (const void*)k_aca_team<T, KIND_RPY, false>);
+  int per_cu = 0, per_cu_t = 0;
   HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, AW_T, 0));
-  HH_REQUIRE(per_cu > 0, HH_ERR_HIP, "ACA kernel does not fit a compute unit");
-  int64_t grid = (int64_t)per_cu * ctx->n_cu;
-  grid = std::min<int64_t>(grid, std::max(std::max(nbig, nhuge), (nb + AW - 1) / AW));
+  HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_t, fnt, AW_T, 0));
+  HH_REQUIRE(per_cu > 0 && per_cu_t > 0, HH_ERR_HIP, "ACA kernel does not fit a compute unit");
+  const int64_t nsmall = nb - nbig - nhuge;
+  // persistent grids: as many workgroups as stay resident
+  const int64_t grid_w = std::min<int64_t>((int64_t)per_cu * ctx->n_cu, (nsmall + AW - 1) / AW);
+  const int64_t grid_t =
+      std::min<int64_t>((int64_t)per_cu_t * ctx->n_cu, std::max(nbig, nhuge));
+  const int64_t grid = std::max(grid_w, grid_t);
   // per worker: Gram history A (l_max (l_max + 1) / 2 3x3 matrices), then the
   // cross-wave partials of a workgroup team [AW][64][9]
   const int64_t half = 9 * ((int64_t)lr->l_max * (lr->l_max + 1) / 2);
@@ -890,8 +957,15 @@ void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
       a.n_huge_wg = (int)nh;
     }
   }
-#define LAUNCH(KIND_, MF_)                                                                  \
-  hipLaunchKernelGGL((k_aca<T, KIND_, MF_>), dim3((unsigned)grid), dim3(AW_T), 0, ctx->stream, a)
+#define LAUNCH(KIND_, MF_)                                                                    \
+  do {                                                                                        \
+    if (grid_t > 0)                                                                           \
+      hipLaunchKernelGGL((k_aca_team<T, KIND_, MF_>), dim3((unsigned)grid_t), dim3(AW_T), 0,   \
+                         ctx->stream, a);                                                     \
+    if (grid_w > 0)                                                                           \
+      hipLaunchKernelGGL((k_aca<T, KIND_, MF_>), dim3((unsigned)grid_w), dim3(AW_T), 0,        \
+                         ctx->stream, a);                                                     \
+  } while (0)
   if (k->kind == KIND_MLP && is_bf16(lr->prec)) {
     if constexpr (sizeof(T) == 4) LAUNCH(KIND_MLP, true);
   } else if (k->kind == KIND_MLP) {

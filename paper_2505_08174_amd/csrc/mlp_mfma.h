@@ -72,81 +72,126 @@ __device__ __forceinline__ void act8(const f32x16& a, int base, bf16x8& hi, bf16
   }
 }
 
-// One hidden layer (64 -> 64): B[4] in, B[4] out (after tanh). ACC adds the
-// products of the activation remainders (W_hi a_lo), for samples whose error
-// must stay far below the cross-approximation tolerance.
-template <bool ACC>
+// One hidden layer (64 -> 64) of NT independent tiles: B[t][4] in, Bo[t][4]
+// out (after tanh). Each weight fragment is read once for all NT tiles, and
+// the tiles' MFMA chains are independent, so one tile's MFMAs overlap the
+// other's activations. ACC adds the products of the activation remainders
+// (W_hi a_lo), for samples whose error must stay far below the
+// cross-approximation tolerance.
+template <bool ACC, int NT>
 __device__ __forceinline__ void hidden_layer(const bf16x8* __restrict__ fr, int base, int lane,
-                                             const bf16x8 (&B)[4], const bf16x8 (&Bl)[4],
-                                             const bf16x8& Bone, bf16x8 (&Bo)[4],
-                                             bf16x8 (&Bol)[4]) {
+                                             const bf16x8 (&B)[NT][4], const bf16x8 (&Bl)[NT][4],
+                                             const bf16x8& Bone, bf16x8 (&Bo)[NT][4],
+                                             bf16x8 (&Bol)[NT][4]) {
 #pragma unroll
   for (int mo = 0; mo < 2; ++mo) {
-    f32x16 acc = {};
-    acc = mfma_bf16(fr[base + (2 * 4 * 2) * 64 + mo * 64 + lane], Bone, acc);   // bias
+    f32x16 acc[NT];
+    const bf16x8 wb = fr[base + (2 * 4 * 2) * 64 + mo * 64 + lane];   // bias
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = mfma_bf16(wb, Bone, f32x16{});
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const bf16x8 wh = fr[base + ((mo * 4 + s) * 2 + 0) * 64 + lane];
-      acc = mfma_bf16(wh, B[s], acc);
-      acc = mfma_bf16(fr[base + ((mo * 4 + s) * 2 + 1) * 64 + lane], B[s], acc);
-      if (ACC) acc = mfma_bf16(wh, Bl[s], acc);
+      const bf16x8 wl = fr[base + ((mo * 4 + s) * 2 + 1) * 64 + lane];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        acc[t] = mfma_bf16(wh, B[t][s], acc[t]);
+        acc[t] = mfma_bf16(wl, B[t][s], acc[t]);
+        if (ACC) acc[t] = mfma_bf16(wh, Bl[t][s], acc[t]);
+      }
     }
-    act8<ACC>(acc, 0, Bo[2 * mo], Bol[2 * mo]);
-    act8<ACC>(acc, 8, Bo[2 * mo + 1], Bol[2 * mo + 1]);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      act8<ACC>(acc[t], 0, Bo[t][2 * mo], Bol[t][2 * mo]);
+      act8<ACC>(acc[t], 8, Bo[t][2 * mo + 1], Bol[t][2 * mo + 1]);
+    }
   }
 }
 
-// Raw outputs o[0..8] of the MLP at input (v0, v1, v2) for this lane's pair.
-// Must be called by all 64 lanes of the wave with lanes l and l+32 holding
-// the same input. ACC = false: activations rounded to BF16 once (relative
-// error ~1e-4 of a sample); ACC = true: activations carried as BF16 hi + lo
-// (~3e-6), used where samples must resolve a 1e-4 cross-approximation.
-template <bool ACC>
-__device__ __forceinline__ void mlp_tile_bf16(const bf16x8* __restrict__ fr, float v0, float v1,
-                                              float v2, float o[9]) {
-  // the fragments are re-read from LDS for every tile: hoisting them out of
+// Raw outputs o[t][0..8] of the MLP at inputs v[t] for this lane's pair of
+// each of NT independent tiles. Must be called by all 64 lanes of the wave
+// with lanes l and l+32 holding the same inputs. ACC = false: activations
+// rounded to BF16 once (relative error ~1e-4 of a sample); ACC = true:
+// activations carried as BF16 hi + lo (~3e-6), used where samples must
+// resolve a 1e-4 cross-approximation.
+template <bool ACC, int NT>
+__device__ __forceinline__ void mlp_tiles_bf16(const bf16x8* __restrict__ fr,
+                                               const float (&v)[NT][3], float (&o)[NT][9]) {
+  // the fragments are re-read from LDS for every call: hoisting them out of
   // a caller's loop would pin 192 VGPRs and cut the occupancy to one wave
   __asm__ volatile("" ::: "memory");
   const int lane = threadIdx.x & 63;
   const bool h1 = lane >= 32;
   const __bf16 z = (__bf16)0.0f, one = (__bf16)1.0f;
-  // layer 1 input column: K slots (v_hi, v_lo, 1, 1 | v_hi, 0...)
-  __bf16 vh0 = (__bf16)v0, vh1 = (__bf16)v1, vh2 = (__bf16)v2;
-  __bf16 vl0 = (__bf16)(v0 - (float)vh0), vl1 = (__bf16)(v1 - (float)vh1),
-         vl2 = (__bf16)(v2 - (float)vh2);
-  bf16x8 b1;
-  b1[0] = vh0; b1[1] = vh1; b1[2] = vh2;
-  b1[3] = h1 ? z : vl0; b1[4] = h1 ? z : vl1; b1[5] = h1 ? z : vl2;
-  b1[6] = h1 ? z : one; b1[7] = h1 ? z : one;
   bf16x8 Bone;
 #pragma unroll
   for (int u = 0; u < 8; ++u) Bone[u] = (!h1 && u < 2) ? one : z;
-  bf16x8 B[4], Bn[4], Bl[4], Bnl[4];
+  // layer 1 input column: K slots (v_hi, v_lo, 1, 1 | v_hi, 0...)
+  bf16x8 b1[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const __bf16 vh0 = (__bf16)v[t][0], vh1 = (__bf16)v[t][1], vh2 = (__bf16)v[t][2];
+    b1[t][0] = vh0;
+    b1[t][1] = vh1;
+    b1[t][2] = vh2;
+    b1[t][3] = h1 ? z : (__bf16)(v[t][0] - (float)vh0);
+    b1[t][4] = h1 ? z : (__bf16)(v[t][1] - (float)vh1);
+    b1[t][5] = h1 ? z : (__bf16)(v[t][2] - (float)vh2);
+    b1[t][6] = h1 ? z : one;
+    b1[t][7] = h1 ? z : one;
+  }
+  bf16x8 B[NT][4], Bn[NT][4], Bl[NT][4], Bnl[NT][4];
 #pragma unroll
   for (int mo = 0; mo < 2; ++mo) {
-    f32x16 acc = {};
-    acc = mfma_bf16(fr[FR_L1 + mo * 64 + lane], b1, acc);
-    act8<ACC>(acc, 0, B[2 * mo], Bl[2 * mo]);
-    act8<ACC>(acc, 8, B[2 * mo + 1], Bl[2 * mo + 1]);
+    const bf16x8 w1 = fr[FR_L1 + mo * 64 + lane];
+    f32x16 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = mfma_bf16(w1, b1[t], f32x16{});
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      act8<ACC>(acc[t], 0, B[t][2 * mo], Bl[t][2 * mo]);
+      act8<ACC>(acc[t], 8, B[t][2 * mo + 1], Bl[t][2 * mo + 1]);
+    }
   }
-  hidden_layer<ACC>(fr, FR_L2, lane, B, Bl, Bone, Bn, Bnl);
-  hidden_layer<ACC>(fr, FR_L3, lane, Bn, Bnl, Bone, B, Bl);
-  f32x16 acc = {};
-  acc = mfma_bf16(fr[FR_L4 + (4 * 2) * 64 + lane], Bone, acc);
+  hidden_layer<ACC, NT>(fr, FR_L2, lane, B, Bl, Bone, Bn, Bnl);
+  hidden_layer<ACC, NT>(fr, FR_L3, lane, Bn, Bnl, Bone, B, Bl);
+  f32x16 acc[NT];
+  const bf16x8 w4b = fr[FR_L4 + (4 * 2) * 64 + lane];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = mfma_bf16(w4b, Bone, f32x16{});
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     const bf16x8 wh = fr[FR_L4 + (s * 2 + 0) * 64 + lane];
-    acc = mfma_bf16(wh, B[s], acc);
-    acc = mfma_bf16(fr[FR_L4 + (s * 2 + 1) * 64 + lane], B[s], acc);
-    if (ACC) acc = mfma_bf16(wh, Bl[s], acc);
+    const bf16x8 wl = fr[FR_L4 + (s * 2 + 1) * 64 + lane];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      acc[t] = mfma_bf16(wh, B[t][s], acc[t]);
+      acc[t] = mfma_bf16(wl, B[t][s], acc[t]);
+      if (ACC) acc[t] = mfma_bf16(wh, Bl[t][s], acc[t]);
+    }
   }
   // rows 0-3 and 8 live in lanes 0-31 (registers 0-3, 4); rows 4-7 in 32-63
-  float t0 = __shfl_xor(acc[0], 32, 64), t1 = __shfl_xor(acc[1], 32, 64);
-  float t2 = __shfl_xor(acc[2], 32, 64), t3 = __shfl_xor(acc[3], 32, 64);
-  float t4 = __shfl_xor(acc[4], 32, 64);
-  o[0] = h1 ? t0 : acc[0]; o[1] = h1 ? t1 : acc[1]; o[2] = h1 ? t2 : acc[2]; o[3] = h1 ? t3 : acc[3];
-  o[4] = h1 ? acc[0] : t0; o[5] = h1 ? acc[1] : t1; o[6] = h1 ? acc[2] : t2; o[7] = h1 ? acc[3] : t3;
-  o[8] = h1 ? t4 : acc[4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const f32x16& c = acc[t];
+    const float t0 = __shfl_xor(c[0], 32, 64), t1 = __shfl_xor(c[1], 32, 64);
+    const float t2 = __shfl_xor(c[2], 32, 64), t3 = __shfl_xor(c[3], 32, 64);
+    const float t4 = __shfl_xor(c[4], 32, 64);
+    o[t][0] = h1 ? t0 : c[0]; o[t][1] = h1 ? t1 : c[1]; o[t][2] = h1 ? t2 : c[2];
+    o[t][3] = h1 ? t3 : c[3]; o[t][4] = h1 ? c[0] : t0; o[t][5] = h1 ? c[1] : t1;
+    o[t][6] = h1 ? c[2] : t2; o[t][7] = h1 ? c[3] : t3; o[t][8] = h1 ? t4 : c[4];
+  }
+}
+
+// One tile of 32 pairs (see mlp_tiles_bf16).
+template <bool ACC>
+__device__ __forceinline__ void mlp_tile_bf16(const bf16x8* __restrict__ fr, float v0, float v1,
+                                              float v2, float o[9]) {
+  const float v[1][3] = {{v0, v1, v2}};
+  float oo[1][9];
+  mlp_tiles_bf16<ACC, 1>(fr, v, oo);
+#pragma unroll
+  for (int e = 0; e < 9; ++e) o[e] = oo[0][e];
 }
 
 // Stage the fragment table (global -> LDS) by the whole workgroup.

@@ -48,6 +48,43 @@ struct NearB {
   int input_mode;
 };
 
+// Adds K(x_i - x_j) F_j for the sources j0, j0 + 1, .., j0 + NT - 1 (one MFMA
+// tile each, evaluated together), in that order.
+template <bool ACC, int NT>
+__device__ __forceinline__ void near_terms(const NearB& a, const bf16x8* fr, bool dir, bool act,
+                                           int ii, double xi0, double xi1, double xi2, int j0,
+                                           double& u0, double& u1, double& u2) {
+  const float c16 = (float)(1.0 / (16.0 * HH_PI));
+  float v[NT][3], rs[NT], o[NT][9];
+  bool skip[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int j = j0 + t;
+    float rx = (float)(xi0 - a.xs[3 * (int64_t)j]);
+    float ry = (float)(xi1 - a.xs[3 * (int64_t)j + 1]);
+    float rz = (float)(xi2 - a.xs[3 * (int64_t)j + 2]);
+    skip[t] = (j == ii) || !act;
+    if (j == ii) { rx = 1.0f; ry = 0.0f; rz = 0.0f; }
+    rs[t] = hh_rsqrt(rx * rx + ry * ry + rz * rz);
+    const float sc = dir ? rs[t] : 1.0f;
+    v[t][0] = rx * sc;
+    v[t][1] = ry * sc;
+    v[t][2] = rz * sc;
+  }
+  mlp_tiles_bf16<ACC, NT>(fr, v, o);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int j = j0 + t;
+    const float sc = skip[t] ? 0.0f : rs[t] * c16;
+    const float f0 = a.Fs[3 * (int64_t)j], f1 = a.Fs[3 * (int64_t)j + 1],
+                f2 = a.Fs[3 * (int64_t)j + 2];
+    const float* q = o[t];
+    u0 += (double)(sc * (2.0f * q[0] * f0 + (q[1] + q[3]) * f1 + (q[2] + q[6]) * f2));
+    u1 += (double)(sc * ((q[3] + q[1]) * f0 + 2.0f * q[4] * f1 + (q[5] + q[7]) * f2));
+    u2 += (double)(sc * ((q[6] + q[2]) * f0 + (q[7] + q[5]) * f1 + 2.0f * q[8] * f2));
+  }
+}
+
 template <bool ACC>
 __global__ __launch_bounds__(NB_T) void k_near_bf16(NearB a) {
   __shared__ bf16x8 fr[FR_TOTAL];
@@ -64,30 +101,15 @@ __global__ __launch_bounds__(NB_T) void k_near_bf16(NearB a) {
   const double xi0 = a.xs[3 * (int64_t)ii], xi1 = a.xs[3 * (int64_t)ii + 1],
                xi2 = a.xs[3 * (int64_t)ii + 2];
   const bool dir = a.input_mode == HH_MLP_INPUT_DIRECTION;
-  const float c16 = (float)(1.0 / (16.0 * HH_PI));
   double u0 = 0, u1 = 0, u2 = 0;
   const int p0 = a.near_ptr[un.x], p1 = a.near_ptr[un.x + 1];
   for (int p = p0; p < p1; ++p) {
     const int4 ns = a.nodes[a.H[p].y];
-    for (int j = ns.x; j < ns.y; ++j) {
-      float rx = (float)(xi0 - a.xs[3 * (int64_t)j]);
-      float ry = (float)(xi1 - a.xs[3 * (int64_t)j + 1]);
-      float rz = (float)(xi2 - a.xs[3 * (int64_t)j + 2]);
-      const bool skip = (j == ii) || !act;
-      if (j == ii) { rx = 1.0f; ry = 0.0f; rz = 0.0f; }
-      const float rs = hh_rsqrt(rx * rx + ry * ry + rz * rz);
-      float o[9];
-      if (dir)
-        mlp_tile_bf16<ACC>(fr, rx * rs, ry * rs, rz * rs, o);
-      else
-        mlp_tile_bf16<ACC>(fr, rx, ry, rz, o);
-      const float sc = skip ? 0.0f : rs * c16;
-      const float f0 = a.Fs[3 * (int64_t)j], f1 = a.Fs[3 * (int64_t)j + 1],
-                  f2 = a.Fs[3 * (int64_t)j + 2];
-      u0 += (double)(sc * (2.0f * o[0] * f0 + (o[1] + o[3]) * f1 + (o[2] + o[6]) * f2));
-      u1 += (double)(sc * ((o[3] + o[1]) * f0 + 2.0f * o[4] * f1 + (o[5] + o[7]) * f2));
-      u2 += (double)(sc * ((o[6] + o[2]) * f0 + (o[7] + o[5]) * f1 + 2.0f * o[8] * f2));
-    }
+    int j = ns.x;
+    // two sources at a time: two independent MFMA chains per wave
+    for (; j + 1 < ns.y; j += 2)
+      near_terms<ACC, 2>(a, fr, dir, act, ii, xi0, xi1, xi2, j, u0, u1, u2);
+    if (j < ns.y) near_terms<ACC, 1>(a, fr, dir, act, ii, xi0, xi1, xi2, j, u0, u1, u2);
   }
   if (act && lane < 32) {
     a.Un[3 * (int64_t)i] = u0;
