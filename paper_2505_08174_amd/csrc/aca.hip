@@ -58,6 +58,7 @@ struct AcaArgs {
   T* huge;              // arenas of the workgroups that take the huge blocks
   int64_t huge_elems;   // elements per huge arena
   int n_huge_wg;        // workgroups blockIdx < n_huge_wg take huge blocks first
+  int64_t slot0_w;      // first worker slot (Gram history, arena) of the single waves
   unsigned long long* pool_top;
   int* overflow;
   int* work;         // dynamic block counter (blocks worked on by single waves)
@@ -851,10 +852,10 @@ __global__ __launch_bounds__(AW_T) void k_aca(AcaArgs<T> a) {
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
   const int64_t wg = blockIdx.x;
   const bool ar = a.arena != nullptr;
-  aca_worker<T, KIND, MF, 1>(a, wl, fr, shw[wv], nullptr, 0, wg * AW + wv, a.work,
+  const int64_t slot = a.slot0_w + wg * AW + wv;
+  aca_worker<T, KIND, MF, 1>(a, wl, fr, shw[wv], nullptr, 0, slot, a.work,
                              a.b0 + a.nhuge + a.nbig, a.b1,
-                             ar ? a.arena + (wg * AW + wv) * a.arena_elems : nullptr,
-                             a.arena_elems);
+                             ar ? a.arena + slot * a.arena_elems : nullptr, a.arena_elems);
 }
 
 template <class T>
@@ -916,12 +917,14 @@ void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
   const int64_t grid_w = std::min<int64_t>((int64_t)per_cu * ctx->n_cu, (nsmall + AW - 1) / AW);
   const int64_t grid_t =
       std::min<int64_t>((int64_t)per_cu_t * ctx->n_cu, std::max(nbig, nhuge));
-  const int64_t grid = std::max(grid_w, grid_t);
+  // the two kernels run concurrently (team kernel on the side stream), so
+  // their workers own disjoint slots: teams [0, grid_t AW), waves after them
+  const int64_t workers = (grid_t + grid_w) * AW;
+  a.slot0_w = grid_t * AW;
   // per worker: Gram history A (l_max (l_max + 1) / 2 3x3 matrices), then the
   // cross-wave partials of a workgroup team [AW][64][9]
   const int64_t half = 9 * ((int64_t)lr->l_max * (lr->l_max + 1) / 2);
   const int64_t stride = half + (int64_t)AW * 64 * 9;
-  const int64_t workers = grid * AW;
   if (lr->gram_workers < workers || lr->gram_stride != stride) {
     lr->gram.alloc(ctx->stream, std::max<int64_t>(1, workers * stride) * sizeof(double));
     lr->gram_workers = workers;
@@ -947,7 +950,7 @@ void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
     if (nhuge > 0) {
       const int64_t fit = (int64_t)(0.5 * (double)ctx->budget_bytes /
                                     ((double)lr->huge_elems * sizeof(T)));
-      const int64_t nh = std::max<int64_t>(1, std::min(grid, fit));
+      const int64_t nh = std::max<int64_t>(1, std::min(std::max<int64_t>(grid_t, 1), fit));
       if (lr->huge_wg < nh) {
         lr->huge.alloc(ctx->stream, nh * lr->huge_elems * sizeof(T));
         lr->huge_wg = nh;
@@ -957,11 +960,19 @@ void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
       a.n_huge_wg = (int)nh;
     }
   }
+  // both kernels: the team kernel on the side stream, forked after the work
+  // queued so far and joined before anything queued later (capturable)
+  const bool both = grid_t > 0 && grid_w > 0;
+  hipStream_t ts = both ? ctx->side : ctx->stream;
+  if (both) {
+    HIP_OK(hipEventRecord(ctx->fork, ctx->stream));
+    HIP_OK(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
+  }
 #define LAUNCH(KIND_, MF_)                                                                    \
   do {                                                                                        \
     if (grid_t > 0)                                                                           \
       hipLaunchKernelGGL((k_aca_team<T, KIND_, MF_>), dim3((unsigned)grid_t), dim3(AW_T), 0,   \
-                         ctx->stream, a);                                                     \
+                         ts, a);                                                              \
     if (grid_w > 0)                                                                           \
       hipLaunchKernelGGL((k_aca<T, KIND_, MF_>), dim3((unsigned)grid_w), dim3(AW_T), 0,        \
                          ctx->stream, a);                                                     \
@@ -975,6 +986,10 @@ void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
   }
 #undef LAUNCH
   HIP_OK(hipGetLastError());
+  if (both) {
+    HIP_OK(hipEventRecord(ctx->join, ctx->side));
+    HIP_OK(hipStreamWaitEvent(ctx->stream, ctx->join, 0));
+  }
 }
 
 __global__ void k_rank_stats(const int32_t* __restrict__ rank, const int32_t* __restrict__ flag,

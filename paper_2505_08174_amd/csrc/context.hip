@@ -207,6 +207,9 @@ hh_status hh_ctx_create(int device, void* stream, hh_ctx* out) {
     ctx->device = device;
     ctx->stream = (hipStream_t)stream;
     HIP_OK(hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, device));
+    HIP_OK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+    HIP_OK(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming));
     // keep freed blocks in the stream-ordered pool for reuse across steps
     hipMemPool_t pool;
     if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
@@ -239,6 +242,12 @@ void hh_ctx_destroy(hh_ctx ctx) {
     (void)hipEventDestroy(r.b);
   }
   for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+  if (ctx->side) {
+    (void)hipStreamSynchronize(ctx->side);
+    (void)hipStreamDestroy(ctx->side);
+  }
+  if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+  if (ctx->join) (void)hipEventDestroy(ctx->join);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
 }

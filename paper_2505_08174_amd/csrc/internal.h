@@ -61,6 +61,10 @@ struct hh_ctx_s {
   int device = 0;
   int n_cu = 1;                // compute units of the device
   hipStream_t stream = nullptr;
+  // second stream (default priority) on which the workgroup-team ACA kernel
+  // runs beside the single-wave kernel, forked from and joined to `stream`
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   std::string last_error;
   DevBuf scratch_flag;   // small device scratch for readbacks (64 x int64)
   int64_t* pinned = nullptr;  // host pinned mirror for readbacks (64 x int64)
