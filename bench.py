@@ -34,9 +34,11 @@ PEAK = {"hbm_GBs": 8000.0, "bf16_TFs": 2500.0, "fp32_TFs": 157.3, "fp64_TFs": 78
 MLP_MAC = 3 * 64 + 64 * 64 + 64 * 64 + 64 * 9      # 8,960 multiply-adds per kernel query
 MLP_FLOP = 2 * MLP_MAC
 MLP_TANH = 3 * 64                                  # activations per kernel query
-# tanh = 1 - 2 / (exp(2x) + 1): two transcendental ops; at a quarter of the
-# FP32 lane rate that is 8 tanh per clock per CU
-TANH_PER_CLK_CU = 8
+# tanh = 1 - 2 / (2^y + 1): two transcendental ops (v_exp_f32, v_rcp_f32). On
+# gfx950 they issue at half the FP32 FMA lane rate, 32 lane-ops per clock per
+# CU (a throughput probe measured 28 for each against 57 for FMA at the clock
+# held under load), so the VALU ceiling is 16 tanh per clock per CU
+TANH_PER_CLK_CU = 16
 CU, CLK = 256, 2.4e9
 # sources whose change invalidates the stored HBM traffic of a kernel
 KERNEL_SOURCES = {"k_aca": ["aca.hip", "mlp_mfma.h", "devmath.h", "internal.h"],

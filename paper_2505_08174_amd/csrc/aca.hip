@@ -56,14 +56,21 @@ struct AcaArgs {
   T* arena;             // per-wave factor arenas (streamed mode)
   int64_t arena_elems;  // elements per wave arena; a workgroup team owns AW of them
   T* huge;              // arenas of the workgroups that take the huge blocks
-  int64_t huge_elems;   // elements per huge arena
-  int n_huge_wg;        // workgroups blockIdx < n_huge_wg take huge blocks first
+  // huge blocks in tiers of one size class each, largest first (streamed
+  // mode): tier t is order[b0 + tier_b[t] .. b0 + tier_b[t+1]); workgroups
+  // [tier_wg[t], tier_wg[t+1]) own arenas of tier_cap[t] elements starting at
+  // huge + tier_off[t], take tier t and then the smaller tiers
+  int ntier;
+  int tier_wg[ACA_MAX_TIERS + 1];
+  int64_t tier_b[ACA_MAX_TIERS + 1];
+  int64_t tier_cap[ACA_MAX_TIERS];
+  int64_t tier_off[ACA_MAX_TIERS];
   int64_t slot0_w;      // first worker slot (Gram history, arena) of the single waves
   unsigned long long* pool_top;
   int* overflow;
   int* work;         // dynamic block counter (blocks worked on by single waves)
   int* work_big;     // dynamic block counter (blocks worked on by whole workgroups)
-  int* work_huge;    // dynamic block counter (huge blocks, streamed mode)
+  int* work_huge;    // dynamic block counters, one per huge tier (streamed mode)
   int64_t nhuge;     // order[b0 .. b0 + nhuge) are huge (streamed mode)
   int64_t nbig;      // then order[.. + nbig) go to whole workgroups
   int64_t b0, b1;    // block range of this launch
@@ -806,9 +813,10 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
 }
 
 // Workgroups of AW waves working as one team per block. Streamed mode: the
-// first n_huge_wg workgroups start on the huge blocks order[b0 .. b0 + nhuge),
-// each in its own large arena. Then every workgroup takes the large blocks
-// (the next nbig in the order, largest first).
+// first tier_wg[ntier] workgroups start on the huge blocks order[b0 .. b0 +
+// nhuge), tier by tier from their own (each in its own large arena). Then
+// every workgroup takes the large blocks (the next nbig in the order, largest
+// first).
 template <class T, int KIND, bool MF>
 __global__ __launch_bounds__(AW_T) void k_aca_team(AcaArgs<T> a) {
   __shared__ T wl[(KIND == KIND_MLP && !MF) ? MLP_NP : 1];
@@ -826,9 +834,21 @@ __global__ __launch_bounds__(AW_T) void k_aca_team(AcaArgs<T> a) {
   const int64_t wg = blockIdx.x;
   const bool ar = a.arena != nullptr;   // streamed mode: arenas, else the shared pool
   const int64_t r1 = a.b0 + a.nhuge, r2 = r1 + a.nbig;
-  if (a.nhuge > 0 && wg < a.n_huge_wg)
-    aca_worker<T, KIND, MF, AW>(a, wl, fr, sh, &tr, wv, wg * AW, a.work_huge, a.b0, r1,
-                                a.huge + wg * a.huge_elems, a.huge_elems);
+  if (a.ntier > 0 && wg < a.tier_wg[a.ntier]) {
+    int t0 = 0;
+    while (wg >= a.tier_wg[t0 + 1]) ++t0;
+    T* own = a.huge + a.tier_off[t0] + (wg - a.tier_wg[t0]) * a.tier_cap[t0];
+#pragma unroll 1
+    for (int tt = t0; tt < a.ntier; ++tt) {
+      // a smaller size class may still need more (a thin block's rank bound
+      // is larger); such a tier is left to its own workgroups
+      if (a.tier_cap[tt] > a.tier_cap[t0]) continue;
+      aca_worker<T, KIND, MF, AW>(a, wl, fr, sh, &tr, wv, wg * AW, a.work_huge + tt,
+                                  a.b0 + a.tier_b[tt], a.b0 + a.tier_b[tt + 1], own,
+                                  a.tier_cap[t0]);
+      __syncthreads();   // sh.bo of the last fetch is read by every wave
+    }
+  }
   __syncthreads();
   aca_worker<T, KIND, MF, AW>(a, wl, fr, sh, &tr, wv, wg * AW, a.work_big, r1, r2,
                               ar ? a.arena + wg * AW * a.arena_elems : nullptr,
@@ -862,7 +882,8 @@ template <class T>
 void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
                   int64_t b0, int64_t b1, T* pool, int64_t pool_elems, void* pool_top,
                   int* overflow, int* work, int* work_big, int* work_huge, int64_t nbig,
-                  int64_t nhuge, const void* Fs, double* ublk, const int64_t* uoff) {
+                  int64_t nhuge, const std::vector<HugeTier>* tiers, int64_t launch_rows,
+                  int64_t team_rows, const void* Fs, double* ublk, const int64_t* uoff) {
   AcaArgs<T> a;
   a.G = p->G.as<int2>();
   a.nG = p->nG;
@@ -913,10 +934,25 @@ void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
   HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_t, fnt, AW_T, 0));
   HH_REQUIRE(per_cu > 0 && per_cu_t > 0, HH_ERR_HIP, "ACA kernel does not fit a compute unit");
   const int64_t nsmall = nb - nbig - nhuge;
-  // persistent grids: as many workgroups as stay resident
-  const int64_t grid_w = std::min<int64_t>((int64_t)per_cu * ctx->n_cu, (nsmall + AW - 1) / AW);
-  const int64_t grid_t =
-      std::min<int64_t>((int64_t)per_cu_t * ctx->n_cu, std::max(nbig, nhuge));
+  // persistent grids on disjoint compute units: the team kernel gets units in
+  // proportion to its estimated share of the work (rows c + q, a team row
+  // costing about 1.15 single-wave rows), the single waves the rest, so that
+  // the two finish together
+  const int64_t ncu = ctx->n_cu;
+  int64_t cu_t = ncu;
+  if (nsmall == 0) {
+    cu_t = ncu;
+  } else if (nbig + nhuge == 0) {
+    cu_t = 0;
+  } else {
+    const double wt = 1.15 * (double)team_rows;
+    const double ws = (double)std::max<int64_t>(launch_rows - team_rows, 0);
+    cu_t = std::min<int64_t>(ncu - 1, std::max<int64_t>(1, llround((double)ncu * wt / (wt + ws))));
+  }
+  const int64_t grid_t = std::min<int64_t>((int64_t)per_cu_t * cu_t, std::max(nbig, nhuge));
+  const int64_t cu_used = (grid_t + per_cu_t - 1) / per_cu_t;
+  const int64_t grid_w =
+      std::min<int64_t>((int64_t)per_cu * (ncu - cu_used), (nsmall + AW - 1) / AW);
   // the two kernels run concurrently (team kernel on the side stream), so
   // their workers own disjoint slots: teams [0, grid_t AW), waves after them
   const int64_t workers = (grid_t + grid_w) * AW;
@@ -936,28 +972,68 @@ void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
   a.arena = nullptr;
   a.arena_elems = 0;
   a.huge = nullptr;
-  a.huge_elems = 0;
-  a.n_huge_wg = 0;
+  a.ntier = 0;
   if (Fs) {
     // streamed mode: a factor arena per wave; huge blocks go to the first
-    // n_huge_wg workgroups, as many arenas of huge_elems as half the budget holds
+    // workgroups of the team grid, in tiers of arenas sized per size class
     if (lr->arena_workers < workers) {
       lr->arena.alloc(ctx->stream, workers * lr->arena_elems * sizeof(T));
       lr->arena_workers = workers;
     }
     a.arena = lr->arena.as<T>();
     a.arena_elems = lr->arena_elems;
-    if (nhuge > 0) {
-      const int64_t fit = (int64_t)(0.5 * (double)ctx->budget_bytes /
-                                    ((double)lr->huge_elems * sizeof(T)));
-      const int64_t nh = std::max<int64_t>(1, std::min(std::max<int64_t>(grid_t, 1), fit));
-      if (lr->huge_wg < nh) {
-        lr->huge.alloc(ctx->stream, nh * lr->huge_elems * sizeof(T));
-        lr->huge_wg = nh;
+    if (nhuge > 0 && tiers && !tiers->empty()) {
+      // workgroups per tier: twice the tier's share of the team's rows c + q
+      // (its share of the samples), at least one, at most its blocks; scaled
+      // down to the team grid and to half the budget
+      const int nt = (int)tiers->size();
+      HH_REQUIRE(nt <= ACA_MAX_TIERS, HH_ERR_CAPACITY, "too many size classes of huge blocks");
+      std::vector<int64_t> nw(nt);
+      const int64_t gt = std::max<int64_t>(grid_t, 1);
+      for (int i = 0; i < nt; ++i) {
+        const HugeTier& h = (*tiers)[i];
+        const double share = (double)h.rows / (double)std::max<int64_t>(team_rows, 1);
+        nw[i] = std::max<int64_t>(1, std::min<int64_t>(h.nblk, (int64_t)ceil(2.0 * gt * share)));
+      }
+      const double cap = 0.5 * (double)ctx->budget_bytes / sizeof(T);
+      for (int pass = 0; pass < 64; ++pass) {
+        int64_t wgs = 0;
+        double mem = 0;
+        for (int i = 0; i < nt; ++i) {
+          wgs += nw[i];
+          mem += (double)nw[i] * (double)(*tiers)[i].need;
+        }
+        const double f = std::min((double)gt / (double)wgs, cap / mem);
+        if (f >= 1.0) break;
+        bool shrunk = false;
+        for (int i = 0; i < nt; ++i) {
+          const int64_t v = std::max<int64_t>(1, (int64_t)floor((double)nw[i] * f));
+          shrunk |= v < nw[i];
+          nw[i] = v;
+        }
+        if (!shrunk) break;   // one workgroup per tier is the floor
+      }
+      int64_t off = 0, b = 0, wgs = 0;
+      for (int i = 0; i < nt; ++i) {
+        const HugeTier& h = (*tiers)[i];
+        a.tier_wg[i] = (int)wgs;
+        a.tier_b[i] = b;
+        a.tier_cap[i] = h.need;
+        a.tier_off[i] = off;
+        wgs += nw[i];
+        b += h.nblk;
+        off += nw[i] * h.need;
+      }
+      a.tier_wg[nt] = (int)wgs;
+      a.tier_b[nt] = b;
+      HH_REQUIRE(wgs <= grid_t, HH_ERR_CAPACITY, "more huge tiers than team workgroups");
+      HH_REQUIRE(b == nhuge, HH_ERR_CAPACITY, "huge tiers do not cover the huge blocks");
+      if (lr->huge_elems < off) {
+        lr->huge.alloc(ctx->stream, off * sizeof(T));
+        lr->huge_elems = off;
       }
       a.huge = lr->huge.as<T>();
-      a.huge_elems = lr->huge_elems;
-      a.n_huge_wg = (int)nh;
+      a.ntier = nt;
     }
   }
   // both kernels: the team kernel on the side stream, forked after the work
@@ -1126,7 +1202,15 @@ void plan_aca(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, int force_streame
   ord.reserve(std::max<int64_t>(nG, 1));
   lr->bounds.assign(1, 0);
   lr->nbig.clear();
+  lr->tiers.clear();
+  lr->launch_rows.clear();
+  lr->team_rows.clear();
   if (!lr->streamed) {
+    int64_t rt = 0, ra = 0;
+    for (int32_t b : big) rt += (int64_t)cs[b] + qs[b];
+    for (int64_t b = 0; b < nG; ++b) ra += (int64_t)cs[b] + qs[b];
+    lr->launch_rows.push_back(ra);
+    lr->team_rows.push_back(rt);
     append_desc(cs, qs, big, ord);
     append_desc(cs, qs, small, ord);
     lr->bounds.push_back(nG);
@@ -1143,13 +1227,11 @@ void plan_aca(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, int force_streame
   const int64_t wave_arena = std::max<int64_t>(arena, 1024);
   const int64_t team_arena = (int64_t)AW * wave_arena;
   std::vector<char> kind(std::max<int64_t>(nG, 1), 0);   // 0 small, 1 large, 2 huge
-  int64_t huge_max = 0;
   for (int32_t b : big) {
     const int64_t cq = (int64_t)cs[b] + qs[b];
     const int64_t kc = std::min<int64_t>(std::min(cs[b], qs[b]), lr->l_max);
     const int64_t w = 9 * cq * kc;
     kind[b] = w > team_arena ? 2 : 1;
-    if (w > team_arena) huge_max = std::max(huge_max, w);
   }
   const int64_t rows_cap = std::max<int64_t>(1, (int64_t)(0.2 * (double)ctx->budget_bytes / 24.0));
   std::vector<int32_t> lid(std::max<int64_t>(nG, 1)), pos(std::max<int64_t>(nG, 1));
@@ -1163,10 +1245,34 @@ void plan_aca(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, int force_streame
     const int32_t r = (int32_t)lr->nbig.size();
     append_desc(cs, qs, hb, ord);
     lr->nhuge.push_back((int64_t)hb.size());
+    // one tier per size class of the huge blocks (contiguous in the order)
+    std::vector<HugeTier> tiers;
+    int prev = -1;
+    for (size_t i = r0; i < ord.size(); ++i) {
+      const int32_t b = ord[i];
+      const int cls = size_cls(cs[b], qs[b]);
+      const int64_t cq = (int64_t)cs[b] + qs[b];
+      const int64_t kc = std::min<int64_t>(std::min(cs[b], qs[b]), lr->l_max);
+      if (cls != prev) tiers.push_back(HugeTier{0, 0, 0});
+      prev = cls;
+      HugeTier& h = tiers.back();
+      h.nblk += 1;
+      h.need = std::max(h.need, 9 * cq * kc);
+      h.rows += cq;
+    }
+    lr->tiers.push_back(tiers);
     append_desc(cs, qs, tb, ord);
     lr->nbig.push_back((int64_t)tb.size());
     append_desc(cs, qs, wb, ord);
     lr->bounds.push_back((int64_t)ord.size());
+    int64_t lrows = 0, trows = 0;
+    const size_t r2 = r0 + hb.size() + tb.size();   // huge and large blocks come first
+    for (size_t i = r0; i < ord.size(); ++i) {
+      lrows += (int64_t)cs[ord[i]] + qs[ord[i]];
+      if (i < r2) trows += (int64_t)cs[ord[i]] + qs[ord[i]];
+    }
+    lr->launch_rows.push_back(lrows);
+    lr->team_rows.push_back(trows);
     for (size_t i = r0; i < ord.size(); ++i) {
       lid[ord[i]] = r;
       pos[ord[i]] = (int32_t)i;
@@ -1185,7 +1291,6 @@ void plan_aca(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, int force_streame
   }
   if (rows > 0 || lr->nbig.empty()) close();
   lr->arena_elems = wave_arena;
-  lr->huge_elems = std::max<int64_t>(huge_max, 1024);
   lr->pool_elems = 1024;   // the shared pool is not used in streamed mode
   lr->ub_elems = std::max<int64_t>(ub_max, 1);
   upload_i32(ctx, lr->order, ord);
@@ -1215,11 +1320,11 @@ void run_aca_stored(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr
       if (lr->prec == HH_FP64)
         launch_aca_t<double>(ctx, t, p, k, lr, 0, nG, lr->pool.as<double>(), lr->pool_elems, top,
                              flags, flags + 1, flags + 2, flags + 3, lr->nbig[0], 0, nullptr,
-                             nullptr, nullptr);
+                             lr->launch_rows[0], lr->team_rows[0], nullptr, nullptr, nullptr);
       else
         launch_aca_t<float>(ctx, t, p, k, lr, 0, nG, lr->pool.as<float>(), lr->pool_elems, top,
                             flags, flags + 1, flags + 2, flags + 3, lr->nbig[0], 0, nullptr,
-                            nullptr, nullptr);
+                            lr->launch_rows[0], lr->team_rows[0], nullptr, nullptr, nullptr);
     }
     HIP_OK(hipMemcpyAsync(ctx->pinned, ctx->scratch_flag.p, 8 * sizeof(int64_t),
                           hipMemcpyDeviceToHost, st));
@@ -1238,19 +1343,23 @@ void run_aca_stored(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr
 }
 
 // Streamed mode, launch i: ACA with the apply fused in; per-block rows go to
-// ublk (offsets uoff[pos] - uoff[b0]). counters: 4 int64 per launch, zeroed.
+// ublk (offsets uoff[pos] - uoff[b0]). counters: ACA_COUNTERS int64 per
+// launch, zeroed.
 void run_aca_batch(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr, size_t i,
                    const void* Fs, int64_t* counters) {
+  static_assert(2 + ACA_MAX_TIERS <= 2 * (ACA_COUNTERS - 1), "counter words");
   int64_t b0 = lr->bounds[i], b1 = lr->bounds[i + 1];
-  int* work = (int*)(counters + 4 * i);   // single waves, workgroups, huge blocks
-  int64_t* top = counters + 4 * i + 2;
+  int* work = (int*)(counters + ACA_COUNTERS * i);   // single waves, workgroups, huge tiers
+  int64_t* top = counters + ACA_COUNTERS * i + ACA_COUNTERS - 1;
   int* ovf = (int*)ctx->scratch_flag.p;
   if (lr->prec == HH_FP64)
     launch_aca_t<double>(ctx, t, p, k, lr, b0, b1, lr->pool.as<double>(), lr->pool_elems, top,
-                         ovf, work, work + 1, work + 2, lr->nbig[i], lr->nhuge[i], Fs,
-                         lr->ublk.as<double>(), lr->uoff.as<int64_t>());
+                         ovf, work, work + 1, work + 2, lr->nbig[i], lr->nhuge[i], &lr->tiers[i],
+                         lr->launch_rows[i], lr->team_rows[i], Fs, lr->ublk.as<double>(),
+                         lr->uoff.as<int64_t>());
   else
     launch_aca_t<float>(ctx, t, p, k, lr, b0, b1, lr->pool.as<float>(), lr->pool_elems, top, ovf,
-                        work, work + 1, work + 2, lr->nbig[i], lr->nhuge[i], Fs,
-                        lr->ublk.as<double>(), lr->uoff.as<int64_t>());
+                        work, work + 1, work + 2, lr->nbig[i], lr->nhuge[i], &lr->tiers[i],
+                        lr->launch_rows[i], lr->team_rows[i], Fs, lr->ublk.as<double>(),
+                        lr->uoff.as<int64_t>());
 }

@@ -253,8 +253,8 @@ void matvec_streamed_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kerne
   }
   zero_words(ctx, Uf.p, 3 * n);
   const size_t nb = lr->bounds.size() - 1;
-  counters.ensure(st, 4 * nb * sizeof(int64_t));
-  zero_words(ctx, counters.p, 4 * (int64_t)nb);
+  counters.ensure(st, ACA_COUNTERS * nb * sizeof(int64_t));
+  zero_words(ctx, counters.p, ACA_COUNTERS * (int64_t)nb);
   if (!lr->pool.p) lr->pool.alloc(st, lr->pool_elems * (lr->prec == HH_FP64 ? 8 : 4));
   if (!lr->ublk.p) lr->ublk.alloc(st, lr->ub_elems * 3 * sizeof(double));
   for (size_t i = 0; i < nb; ++i) {

@@ -158,6 +158,17 @@ struct hh_part_s {
 
 #define LMAX_CAP 64
 
+// Huge blocks of one size class in a launch (streamed mode): their count,
+// the factor elements the largest of them may need, and their rows c + q.
+struct HugeTier {
+  int64_t nblk, need, rows;
+};
+
+// Work counters per launch range (int64 words): single waves, workgroups and
+// up to ACA_MAX_TIERS huge tiers (ints), then the pool top (int64).
+#define ACA_MAX_TIERS 20
+#define ACA_COUNTERS 16
+
 struct hh_lowrank_s {
   hh_ctx ctx = nullptr;
   hh_part part = nullptr;
@@ -186,11 +197,15 @@ struct hh_lowrank_s {
   DevBuf arena;                  // per-wave factor arenas (streamed mode)
   int64_t arena_elems = 0, arena_workers = 0;
   DevBuf huge;                   // arenas of the workgroups taking huge blocks
-  int64_t huge_elems = 0, huge_wg = 0;
+  int64_t huge_elems = 0;        // elements allocated in `huge`
   DevBuf ublk;                   // double [ub_elems][3]
   DevBuf order;                  // int32 [nG] ACA work order (largest blocks first)
   std::vector<int64_t> nbig;     // per launch range: blocks for whole workgroups
   std::vector<int64_t> nhuge;    // per launch range: huge blocks (streamed mode)
+  // per launch range: the huge blocks by size class, largest first (one tier
+  // per class), and the rows c + q of the whole range
+  std::vector<std::vector<HugeTier>> tiers;
+  std::vector<int64_t> launch_rows, team_rows;   // rows c + q: all blocks, team blocks
   // product workspaces, kept between products (sorted F, near rows, far rows,
   // work counters)
   DevBuf ws_f, ws_near, ws_far, ws_cnt;
