@@ -85,7 +85,11 @@ typedef enum { HH_MLP_INPUT_DIRECTION = 0, HH_MLP_INPUT_DISPLACEMENT = 1 } hh_ml
 /* ---------------------------------------------------------------- context */
 
 /* Create a context on HIP device `device` that enqueues on `stream`
- * (a hipStream_t; NULL = the null stream). */
+ * (a hipStream_t; NULL = the null stream). The context also owns a second
+ * stream (default priority, non-blocking) and two events: the ACA runs its
+ * workgroup-team kernel there, forked from `stream` and joined back before
+ * any later work on `stream`, so callers only ever order against `stream`.
+ * Released by hh_ctx_destroy. */
 hh_status hh_ctx_create(int device, void* stream, hh_ctx* out);
 void hh_ctx_destroy(hh_ctx ctx);
 const char* hh_last_error(hh_ctx ctx);

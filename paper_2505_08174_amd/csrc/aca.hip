@@ -934,26 +934,29 @@ void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
   HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_t, fnt, AW_T, 0));
   HH_REQUIRE(per_cu > 0 && per_cu_t > 0, HH_ERR_HIP, "ACA kernel does not fit a compute unit");
   const int64_t nsmall = nb - nbig - nhuge;
-  // persistent grids on disjoint compute units: the team kernel gets units in
-  // proportion to its estimated share of the work (rows c + q, a team row
-  // costing about 1.15 single-wave rows), the single waves the rest, so that
-  // the two finish together
+  // persistent grids. When huge blocks hold a sizeable part of the work
+  // (their long tail would leave the GPU idle behind the team kernel), the two
+  // kernels run concurrently on disjoint compute units: the team kernel gets
+  // units in proportion to its estimated share of the work (rows c + q, a team
+  // row costing about 1.15 single-wave rows), the single waves the rest, so
+  // that the two finish together. Otherwise each kernel in turn gets them all.
+  int64_t huge_rows = 0;
+  if (tiers)
+    for (const HugeTier& h : *tiers) huge_rows += h.rows;
+  const bool split = Fs != nullptr && nsmall > 0 && nbig + nhuge > 0 &&
+                     (double)huge_rows >= 0.05 * (double)launch_rows;
   const int64_t ncu = ctx->n_cu;
   int64_t cu_t = ncu;
-  if (nsmall == 0) {
-    cu_t = ncu;
-  } else if (nbig + nhuge == 0) {
-    cu_t = 0;
-  } else {
+  if (split) {
     const double wt = 1.15 * (double)team_rows;
     const double ws = (double)std::max<int64_t>(launch_rows - team_rows, 0);
     cu_t = std::min<int64_t>(ncu - 1, std::max<int64_t>(1, llround((double)ncu * wt / (wt + ws))));
   }
   const int64_t grid_t = std::min<int64_t>((int64_t)per_cu_t * cu_t, std::max(nbig, nhuge));
-  const int64_t cu_used = (grid_t + per_cu_t - 1) / per_cu_t;
+  const int64_t cu_used = split ? (grid_t + per_cu_t - 1) / per_cu_t : 0;
   const int64_t grid_w =
       std::min<int64_t>((int64_t)per_cu * (ncu - cu_used), (nsmall + AW - 1) / AW);
-  // the two kernels run concurrently (team kernel on the side stream), so
+  // the two kernels may run concurrently (team kernel on the side stream), so
   // their workers own disjoint slots: teams [0, grid_t AW), waves after them
   const int64_t workers = (grid_t + grid_w) * AW;
   a.slot0_w = grid_t * AW;
@@ -1036,9 +1039,9 @@ void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
       a.ntier = nt;
     }
   }
-  // both kernels: the team kernel on the side stream, forked after the work
-  // queued so far and joined before anything queued later (capturable)
-  const bool both = grid_t > 0 && grid_w > 0;
+  // concurrent kernels: the team kernel on the side stream, forked after the
+  // work queued so far and joined before anything queued later (capturable)
+  const bool both = split && grid_t > 0 && grid_w > 0;
   hipStream_t ts = both ? ctx->side : ctx->stream;
   if (both) {
     HIP_OK(hipEventRecord(ctx->fork, ctx->stream));
