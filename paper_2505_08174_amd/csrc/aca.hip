@@ -135,12 +135,41 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// v + (v of the source lane given by a DPP control), 0 where the source lane
+// is outside the row or the row is masked off
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  int slo, shi;
+  if (ROW_MASK == 0xf) {   // every row written; invalid source lanes read 0
+    slo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, true);
+    shi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, true);
+  } else {                 // rows masked off keep the 0 they start from
+    slo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xf, false);
+    shi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xf, false);
+  }
+  return v + __hiloint2double(shi, slo);
+}
+
+// Sum over the wave of each p[e], returned in every lane: scans by row shifts 1, 2,
+// 4, 8 inside each 16-lane row (lane 15 of a row then holds the row sum), row
+// 0 into row 1 and row 2 into row 3 (lane 15 broadcast), rows 0-1 into rows
+// 2-3 (lane 31 broadcast), so lane 63 holds the total. No LDS traffic.
 template <int N>
 __device__ __forceinline__ void wave_sumv(double (&p)[N]) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-    for (int e = 0; e < N; ++e) p[e] += __shfl_xor(p[e], o, 64);
+  for (int e = 0; e < N; ++e) {
+    double v = p[e];
+    v = dpp_add<0x111, 0xf>(v);   // row_shr:1
+    v = dpp_add<0x112, 0xf>(v);   // row_shr:2
+    v = dpp_add<0x114, 0xf>(v);   // row_shr:4
+    v = dpp_add<0x118, 0xf>(v);   // row_shr:8
+    v = dpp_add<0x142, 0xa>(v);   // row_bcast:15 into rows 1, 3
+    v = dpp_add<0x143, 0xc>(v);   // row_bcast:31 into rows 2, 3
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    p[e] = __hiloint2double(hi, lo);
+  }
 }
 
 template <class T>
