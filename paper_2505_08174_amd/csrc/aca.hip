@@ -985,10 +985,11 @@ void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
   const int64_t cu_used = split ? (grid_t + per_cu_t - 1) / per_cu_t : 0;
   const int64_t grid_w =
       std::min<int64_t>((int64_t)per_cu * (ncu - cu_used), (nsmall + AW - 1) / AW);
-  // the two kernels may run concurrently (team kernel on the side stream), so
-  // their workers own disjoint slots: teams [0, grid_t AW), waves after them
-  const int64_t workers = (grid_t + grid_w) * AW;
-  a.slot0_w = grid_t * AW;
+  // concurrent kernels (team kernel on the side stream) give their workers
+  // disjoint slots, teams [0, grid_t AW) and the single waves after them;
+  // kernels in turn share the slots
+  const int64_t workers = split ? (grid_t + grid_w) * AW : std::max(grid_t, grid_w) * AW;
+  a.slot0_w = split ? grid_t * AW : 0;
   // per worker: Gram history A (l_max (l_max + 1) / 2 3x3 matrices), then the
   // cross-wave partials of a workgroup team [AW][64][9]
   const int64_t half = 9 * ((int64_t)lr->l_max * (lr->l_max + 1) / 2);
