@@ -183,7 +183,10 @@ hh_status hh_aca_build(hh_ctx ctx, hh_tree tree, hh_part part, hh_kernel kern,
  * precision. Does not sync. Workspaces live in lr: the first call sizes
  * them; later calls allocate nothing and record no memset, so they can be
  * captured in a HIP graph (with profiling off). Products on one lr must not
- * overlap in time. */
+ * overlap in time. In streamed mode, where huge blocks hold 5% or more of a
+ * launch's rows, the ACA's workgroup-team kernel runs on the context's second
+ * stream, forked from and joined back to the context stream inside this call
+ * (a capture includes it). */
 hh_status hh_matvec(hh_ctx ctx, hh_tree tree, hh_part part, hh_lowrank lr, hh_kernel kern,
                     hh_precision prec, const void* F, void* U);
 
