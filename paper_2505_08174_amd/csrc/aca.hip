@@ -561,6 +561,9 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
       double P[9];
 #pragma unroll
       for (int e = 0; e < 9; ++e) P[e] = (double)Ck[9 * (int64_t)bi + e];
+      // every wave of a team holds P before the normalisation below
+      // overwrites row i_k (a single wave loads it before it stores)
+      if constexpr (TW > 1) __syncthreads();
       const double det = P[0] * (P[4] * P[8] - P[5] * P[7]) - P[1] * (P[3] * P[8] - P[5] * P[6]) +
                          P[2] * (P[3] * P[7] - P[4] * P[6]);
       double fro2 = 0;
