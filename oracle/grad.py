@@ -94,6 +94,36 @@ def dense_grad_mlp(X, F, w, mlp, chunk_pairs: int = 1 << 16, inp: str = "directi
     return dX, dW, db
 
 
+def dense_grad_rows(X, F, w, kern, rows):
+    """Rows `rows` of the dense gradients, for sizes where the full sums are
+    too costly: (dL/dF [k, 3], dL/dX [k, 3] or None for a kernel other than
+    the MLP). dL/dF_j = alpha_1 w_j + sum_{i != j} K(x_i - x_j)^T w_i, and
+    dL/dx_i = sum_{j != i} grad_r (w_i^T K(r) F_j)|_{r = x_i - x_j}
+            - sum_{j != i} grad_r (w_j^T K(r) F_i)|_{r = x_j - x_i}
+    (the particle is the target of the first pairs and the source of the
+    second), each pair term back-propagated by kernel_vjp."""
+    X = np.asarray(X, dtype=np.float64)
+    F = np.asarray(F, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    rows = np.asarray(rows, dtype=np.int64)
+    n = X.shape[0]
+    dF = np.empty((rows.size, 3))
+    dX = np.empty((rows.size, 3)) if kern.mlp is not None else None
+    for a, i in enumerate(rows):
+        others = np.arange(n)
+        others = others[others != i]
+        K = kern(X[others] - X[i])                          # K(x_o - x_i), i the source
+        dF[a] = kern.alpha1 * w[i] + np.einsum("pab,pa->b", K, w[others])
+        if dX is None:
+            continue
+        g_t = np.einsum("a,pb->pab", w[i], F[others])       # i the target: w_i F_j^T
+        dr_t, _, _ = kernel_vjp(X[i] - X[others], g_t, kern.mlp, kern.inp)
+        g_s = np.einsum("pa,b->pab", w[others], F[i])       # i the source: w_j F_i^T
+        dr_s, _, _ = kernel_vjp(X[others] - X[i], g_s, kern.mlp, kern.inp)
+        dX[a] = dr_t.sum(axis=0) - dr_s.sum(axis=0)
+    return dF, dX
+
+
 # --------------------------------------------------------------------------
 # Adjoint of the H-matrix product with its structure frozen: the tree, the
 # partition, the ACA pivots and ranks (and which blocks fell back) stay as in

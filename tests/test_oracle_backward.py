@@ -87,3 +87,35 @@ def test_grad_X_theta_finite_differences():
             return L(X, kernels.Kernel("mlp", kernels.MLP(W2, bs)))
         fd = (Lw(h) - Lw(-h)) / (2 * h)
         assert abs(fd - dW[l][idx]) <= 1e-6 * max(1.0, abs(fd)), (l, idx, fd, dW[l][idx])
+
+
+def test_adjoint_displacement_input_finite_differences():
+    """The frozen-structure adjoint with the raw-displacement MLP input (the
+    kernel is then not asymptotically smooth and many blocks fall back)."""
+    X = wl.rsa_cube(260, 0.15, seed=21)
+    F = wl.normal_forces(260, seed=21)
+    w = wl.normal_forces(260, seed=71)
+    mlp = kernels.MLP(*wl.mlp_weights(1))
+    kern = kernels.Kernel("mlp", mlp, inp="displacement")
+    hm = hmatvec.build(X, kern, 16, 1.0, 1e-5, 48)
+    assert len(hm.G) > 10
+    dF, dX, dW, db = grad.hmatvec_grad(hm, X, F, w, kern)
+    L = lambda X_, k_: float(np.sum(w * grad.frozen_apply(hm, X_, F, k_)))
+    h = 1e-5
+    for (p, d) in [(3, 0), (77, 2)]:
+        Xp, Xm = X.copy(), X.copy()
+        Xp[p, d] += h
+        Xm[p, d] -= h
+        fd = (L(Xp, kern) - L(Xm, kern)) / (2 * h)
+        assert abs(fd - dX[p, d]) <= 1e-6 * max(1.0, abs(fd)), (p, d, fd, dX[p, d])
+    W2 = [m.copy() for m in mlp.W]
+    W2[2][5, 9] += h
+    W3 = [m.copy() for m in mlp.W]
+    W3[2][5, 9] -= h
+    fd = (L(X, kernels.Kernel("mlp", kernels.MLP(W2, mlp.b), inp="displacement")) -
+          L(X, kernels.Kernel("mlp", kernels.MLP(W3, mlp.b), inp="displacement"))) / (2 * h)
+    assert abs(fd - dW[2][5, 9]) <= 1e-6 * max(1.0, abs(fd))
+    # dL/dF is the transposed frozen product
+    e = wl.normal_forces(260, seed=5)
+    assert abs(float(np.sum(dF * e)) - float(np.sum(w * grad.frozen_apply(hm, X, e, kern)))) \
+        <= 1e-11 * abs(float(np.sum(dF * e)))
