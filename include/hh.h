@@ -154,6 +154,16 @@ hh_status hh_build_tree_batch(hh_ctx ctx, const double* X, const int64_t* offset
 hh_status hh_build_tree_batch_leaf(hh_ctx ctx, const double* X, const int64_t* offsets,
                                    int32_t n_sys, const int32_t* c_leafs, hh_tree* out);
 
+/* New positions for an existing tree, keeping its particle order, nodes and
+ * leaves (Definition 1's clusters as index sets) and recomputing the sorted
+ * positions and the tight boxes of every node. X: device FP64 [n][3] in the
+ * caller's order. The Morton keys are not recomputed, and a partition built
+ * on the tree keeps its blocks (Eq. (7) is not re-tested). Used to evaluate
+ * the frozen-structure product at perturbed positions (finite differences
+ * of hh_matvec_backward) and for time steps that keep the structure.
+ * Non-finite X -> HH_ERR_INVALID_ARG. Syncs. */
+hh_status hh_tree_refit(hh_ctx ctx, hh_tree tree, const double* X);
+
 /* Block partition (Algorithm 1) with the admissibility test Eq. (7) on tight
  * bounding boxes of the member centres: admissible iff dist^2 > 0 and
  * max(diam_tau^2, diam_sigma^2) <= eta^2 dist^2. eta > 0. dense_mode != 0
@@ -172,9 +182,29 @@ hh_status hh_partition(hh_ctx ctx, hh_tree tree, double eta, int dense_mode, hh_
  * hh_lowrank_info). eps >= 0, 1 <= l_max <= 64. Syncs.
  * When the factors would not fit half the context budget the handle is in
  * streamed mode: this call only plans, and hh_matvec runs the ACA with the
- * product fused in and keeps no factors (Sec. 3.3.2). */
+ * product fused in and keeps no factors (Sec. 3.3.2).
+ * freeze_pivots_from (nullable): a stored-mode handle built on the same
+ * partition. The recursion of Algorithm 2 is then replayed with its pivots
+ * (i_k, j_k), ranks and dense fallbacks instead of searching and testing
+ * (eps and l_max are ignored); kern may differ from the one it was built
+ * with. Together with hh_tree_refit this evaluates the frozen-structure
+ * product at new positions or kernel parameters, the function whose
+ * derivatives hh_matvec_backward returns. A pivot entry that is singular at
+ * the new positions turns its block into a dense fallback. HH_FP64 and
+ * HH_FP32 only; a streamed source -> HH_ERR_INVALID_ARG. */
 hh_status hh_aca_build(hh_ctx ctx, hh_tree tree, hh_part part, hh_kernel kern,
-                       hh_precision prec, double eps, int32_t l_max, hh_lowrank* out);
+                       hh_precision prec, double eps, int32_t l_max,
+                       hh_lowrank freeze_pivots_from, hh_lowrank* out);
+
+/* As hh_aca_build with freeze_pivots_from, with the pivots given in host
+ * arrays in the layout of hh_lowrank_export: rank[nG], fallback[nG] (0 or 1;
+ * a block with 1 is evaluated densely), piv_i[nG][64] and piv_j[nG][64]
+ * (local row and column indices, entries past the rank ignored). Blocks are
+ * in the partition's order. Ranks must lie in [0, min(c, q, 64)] and pivots
+ * inside the block, else HH_ERR_INVALID_ARG. HH_FP64 and HH_FP32 only. Syncs. */
+hh_status hh_aca_build_pivots(hh_ctx ctx, hh_tree tree, hh_part part, hh_kernel kern,
+                              hh_precision prec, const int32_t* rank, const int32_t* fallback,
+                              const int32_t* piv_i, const int32_t* piv_j, hh_lowrank* out);
 
 /* U = alpha_1 F + sum_{P^H} H F + sum_{P^G} C (Q F)  (Eq. (6), first two
  * terms). F: device [n][3] (FP64 for HH_FP64, FP32 otherwise). U: device

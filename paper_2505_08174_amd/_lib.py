@@ -40,7 +40,10 @@ SIGNATURES = {
     "hh_build_tree_batch_leaf": (C.c_int, [_vp, _vp, _pi64, _i32, C.POINTER(_i32),
                                            C.POINTER(_vp)]),
     "hh_partition": (C.c_int, [_vp, _vp, _d, C.c_int, C.POINTER(_vp)]),
-    "hh_aca_build": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int, _d, _i32, C.POINTER(_vp)]),
+    "hh_aca_build": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int, _d, _i32, _vp, C.POINTER(_vp)]),
+    "hh_aca_build_pivots": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int, _pi32, _pi32, _pi32, _pi32,
+                                      C.POINTER(_vp)]),
+    "hh_tree_refit": (C.c_int, [_vp, _vp, _vp]),
     "hh_matvec": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int, _vp, _vp]),
     "hh_matvec_backward": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int, _vp, _vp, _vp, _vp, _vp]),
     "hh_tree_free": (None, [_vp]),

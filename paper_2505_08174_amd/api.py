@@ -234,11 +234,45 @@ def partition(ctx: Context, tree: Tree, eta: float = 1.0, dense_mode: bool = Fal
 
 
 def aca_build(ctx: Context, tree: Tree, part: Partition, kern: Kernel, prec="fp64",
-              eps: float = 1e-6, l_max: int = 48) -> LowRank:
+              eps: float = 1e-6, l_max: int = 48, freeze_pivots_from: LowRank | None = None
+              ) -> LowRank:
+    """ACA of every admissible block; with freeze_pivots_from, the recursion
+    replayed with that handle's pivots, ranks and fallbacks."""
     h = C.c_void_p()
+    fz = freeze_pivots_from.h if freeze_pivots_from is not None else C.c_void_p(0)
     ctx.check(L.load().hh_aca_build(ctx.h, tree.h, part.h, kern.h, _prec(prec), float(eps),
-                                    int(l_max), C.byref(h)))
+                                    int(l_max), fz, C.byref(h)))
     return LowRank(ctx, h, keep=(tree, part, kern))
+
+
+def aca_build_pivots(ctx: Context, tree: Tree, part: Partition, kern: Kernel, prec, rank,
+                     fallback, piv_i, piv_j) -> LowRank:
+    """Factors from the ACA recursion with the given pivots (host arrays:
+    rank [nG], fallback [nG], piv_i and piv_j [nG, 64])."""
+    ng = part.info()[0]
+    rk = np.ascontiguousarray(rank, dtype=np.int32)
+    fb = np.ascontiguousarray(fallback, dtype=np.int32)
+    pi = np.full((max(ng, 1), L.LMAX_CAP), -1, np.int32)
+    pj = np.full((max(ng, 1), L.LMAX_CAP), -1, np.int32)
+    if ng:
+        pi[:ng, :np.shape(piv_i)[1]] = piv_i
+        pj[:ng, :np.shape(piv_j)[1]] = piv_j
+    assert rk.shape == (ng,) and fb.shape == (ng,)
+    p32 = C.POINTER(C.c_int32)
+    h = C.c_void_p()
+    ctx.check(L.load().hh_aca_build_pivots(ctx.h, tree.h, part.h, kern.h, _prec(prec),
+                                           rk.ctypes.data_as(p32), fb.ctypes.data_as(p32),
+                                           pi.ctypes.data_as(p32), pj.ctypes.data_as(p32),
+                                           C.byref(h)))
+    return LowRank(ctx, h, keep=(tree, part, kern))
+
+
+def tree_refit(ctx: Context, tree: Tree, X: torch.Tensor) -> Tree:
+    """New positions for `tree`, keeping its order and nodes (in place)."""
+    assert X.is_cuda and X.dtype == torch.float64 and X.shape == (tree.info()[0], 3)
+    X = X.contiguous()
+    ctx.check(L.load().hh_tree_refit(ctx.h, tree.h, _ptr(X)))
+    return tree
 
 
 def matvec(ctx: Context, tree: Tree, part: Partition, lr: LowRank, kern: Kernel, F: torch.Tensor,

@@ -19,7 +19,9 @@
 // without a new term; |det P| <= 1e-14 ||P||_F^3 ends with a dense fallback;
 // l_max terms without convergence end with a dense fallback.
 // Factors c_k (c entries) and q_k (q entries), 9 values each, are stored
-// contiguously per step in a pool; each step bump-allocates 9 (c + q) values.
+// contiguously per step in a pool, followed by the pivot entry P_k (9 values);
+// each step bump-allocates 9 (c + q + 1) values. In streamed mode the factors
+// of a step take 9 (c + q) values of the worker's arena.
 // Samples, residuals and factors are in the working type T; pivots, norms
 // and Gram matrices in FP64 in every form. In the BF16 form the samples come
 // from the MFMA MLP tile (activations carried as BF16 hi + lo).
@@ -418,7 +420,8 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
     for (int k = 0; k < kmax; ++k) {
       team_sync<TW>();   // sh.bo and sh.qc of the previous step are consumed
       if (lead) {
-        const unsigned long long need = 9ull * (unsigned long long)(c + q);
+        // c_k, q_k and (stored factors) the pivot entry P_k for the adjoint
+        const unsigned long long need = 9ull * (unsigned long long)(c + q + (fuse ? 0 : 1));
         unsigned long long o;
         int ovf = 0;
         if (own) {
@@ -561,6 +564,13 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
       double P[9];
 #pragma unroll
       for (int e = 0; e < 9; ++e) P[e] = (double)Ck[9 * (int64_t)bi + e];
+      // stored factors keep the pivot entry P_k = a(i_k) after q_k (the
+      // backward differentiates c_k = a P_k^-1 with the P_k that was used)
+      if (!fuse && lead) {
+        T* ps = Ck + 9 * (int64_t)(c + q);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) ps[e] = Ck[9 * (int64_t)bi + e];
+      }
       // every wave of a team holds P before the normalisation below
       // overwrites row i_k (a single wave loads it before it stores)
       if constexpr (TW > 1) __syncthreads();
@@ -922,13 +932,7 @@ void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
   a.order = lr->order.as<int32_t>();
   a.nodes = t->nodes.as<int4>();
   a.xs = t->xs.as<double>();
-  a.kp.kind = k->kind;
-  a.kp.input_mode = k->input_mode;
-  a.kp.a = k->a;
-  a.kp.c8 = 1.0 / (8.0 * HH_PI * k->mu);
-  a.kp.c6 = 1.0 / (6.0 * HH_PI * k->mu * k->a);
-  a.kp.alpha1 = k->alpha1;
-  a.kp.w = sizeof(T) == 8 ? k->p64.p : k->p32.p;
+  a.kp = make_kparams(k, sizeof(T) == 8);
   a.eps2 = lr->eps * lr->eps;
   a.l_max = lr->l_max;
   a.rank = lr->rank.as<int32_t>();
@@ -1158,8 +1162,8 @@ void lowrank_stats(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, bool toff) {
 }
 
 // Sizes of every admissible block (host), used to plan storage.
-static void block_sizes(hh_ctx ctx, hh_tree t, hh_part p, std::vector<int32_t>& cs,
-                        std::vector<int32_t>& qs) {
+void block_sizes(hh_ctx ctx, hh_tree t, hh_part p, std::vector<int32_t>& cs,
+                 std::vector<int32_t>& qs) {
   int64_t nG = p->nG;
   std::vector<int4> nodes(t->n_nodes);
   std::vector<int2> G(nG);
@@ -1224,7 +1228,7 @@ void plan_aca(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, int force_streame
   for (int64_t b = 0; b < nG; ++b) {
     const int64_t cq = (int64_t)cs[b] + qs[b];
     const int64_t kc = std::min<int64_t>(std::min(cs[b], qs[b]), lr->l_max);
-    est += 9 * cq * std::min<int64_t>(kc, 20);
+    est += 9 * (cq + 1) * std::min<int64_t>(kc, 20);
     if (size_cls(cs[b], qs[b]) >= ctx->team_cls) {
       big.push_back((int32_t)b);
     } else {

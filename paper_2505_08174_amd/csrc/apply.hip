@@ -18,6 +18,9 @@ void run_aca_stored(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr
 void run_aca_batch(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr, size_t i,
                    const void* Fs, int64_t* counters);
 void lowrank_stats(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, bool toff);
+hh_lowrank_s* build_lowrank_pivots(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, int prec,
+                                   const int32_t* rank, const int32_t* fallback,
+                                   const int32_t* piv_i, const int32_t* piv_j);
 
 namespace {
 
@@ -181,18 +184,6 @@ __global__ __launch_bounds__(T256) void k_final(int64_t n, const int32_t* __rest
     U[3 * o + d] = (TO)(((double)Un[3 * s + d] + Uf[3 * s + d]) + alpha1 * (double)Fs[3 * s + d]);
 }
 
-KParams make_kparams(hh_kernel k, bool fp64) {
-  KParams kp;
-  kp.kind = k->kind;
-  kp.input_mode = k->input_mode;
-  kp.a = k->a;
-  kp.c8 = 1.0 / (8.0 * HH_PI * k->mu);
-  kp.c6 = 1.0 / (6.0 * HH_PI * k->mu * k->a);
-  kp.alpha1 = k->alpha1;
-  kp.w = fp64 ? k->p64.p : k->p32.p;
-  return kp;
-}
-
 template <class T, class TI, class TO, class TU>
 void matvec_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kernel k, const void* F,
               void* U) {
@@ -285,31 +276,59 @@ void matvec_streamed_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kerne
 extern "C" {
 
 hh_status hh_aca_build(hh_ctx ctx, hh_tree tree, hh_part part, hh_kernel kern,
-                       hh_precision prec, double eps, int32_t l_max, hh_lowrank* out) {
+                       hh_precision prec, double eps, int32_t l_max,
+                       hh_lowrank freeze_pivots_from, hh_lowrank* out) {
   if (out) *out = nullptr;
   HH_API_BEGIN(ctx)
   HH_REQUIRE(out && tree && part && kern, HH_ERR_INVALID_ARG, "NULL argument");
   HH_REQUIRE(part->tree == tree, HH_ERR_INVALID_ARG, "partition was built on another tree");
-  HH_REQUIRE(prec == HH_FP64 || prec == HH_FP32 || is_bf16(prec), HH_ERR_INVALID_ARG,
-             "unknown precision");
-  HH_REQUIRE(eps >= 0.0 && eps < INFINITY, HH_ERR_INVALID_ARG, "eps must be >= 0");
-  HH_REQUIRE(l_max >= 1 && l_max <= LMAX_CAP, HH_ERR_INVALID_ARG, "l_max must be in [1, 64]");
-  hh_lowrank_s* lr = new hh_lowrank_s();
-  try {
-    lr->ctx = ctx;
-    lr->part = part;
-    lr->prec = prec;
-    lr->nG = part->nG;
-    lr->l_max = l_max;
-    lr->eps = eps;
-    lr->kern = kern;
-    plan_aca(ctx, tree, part, lr, 0);
-    if (!lr->streamed) run_aca_stored(ctx, tree, part, kern, lr);
-  } catch (...) {
-    delete lr;
-    throw;
+  if (freeze_pivots_from) {
+    // the recursion replayed with the pivots, ranks and fallbacks of an
+    // earlier build on the same partition (eps and l_max unused)
+    hh_lowrank src = freeze_pivots_from;
+    HH_REQUIRE(src->part == part, HH_ERR_INVALID_ARG,
+               "freeze_pivots_from was built on another partition");
+    HH_REQUIRE(!src->streamed, HH_ERR_INVALID_ARG,
+               "freeze_pivots_from must hold stored factors (streamed mode keeps none)");
+    const int64_t nG = part->nG;
+    std::vector<int32_t> rk(std::max<int64_t>(nG, 1)), fb(std::max<int64_t>(nG, 1));
+    std::vector<int32_t> pv(std::max<int64_t>(nG, 1) * 2 * LMAX_CAP);
+    std::vector<int32_t> pi(std::max<int64_t>(nG, 1) * LMAX_CAP),
+        pj(std::max<int64_t>(nG, 1) * LMAX_CAP);
+    if (nG > 0) {
+      read_bytes(ctx, rk.data(), src->rank.p, nG * sizeof(int32_t));
+      read_bytes(ctx, fb.data(), src->flag.p, nG * sizeof(int32_t));
+      read_bytes(ctx, pv.data(), src->piv.p, nG * 2 * LMAX_CAP * sizeof(int32_t));
+    }
+    for (int64_t b = 0; b < nG; ++b)
+      for (int m = 0; m < LMAX_CAP; ++m) {
+        pi[b * LMAX_CAP + m] = pv[b * 2 * LMAX_CAP + m];
+        pj[b * LMAX_CAP + m] = pv[b * 2 * LMAX_CAP + LMAX_CAP + m];
+      }
+    *out = build_lowrank_pivots(ctx, tree, part, kern, prec, rk.data(), fb.data(), pi.data(),
+                                pj.data());
+  } else {
+    HH_REQUIRE(prec == HH_FP64 || prec == HH_FP32 || is_bf16(prec), HH_ERR_INVALID_ARG,
+               "unknown precision");
+    HH_REQUIRE(eps >= 0.0 && eps < INFINITY, HH_ERR_INVALID_ARG, "eps must be >= 0");
+    HH_REQUIRE(l_max >= 1 && l_max <= LMAX_CAP, HH_ERR_INVALID_ARG, "l_max must be in [1, 64]");
+    hh_lowrank_s* lr = new hh_lowrank_s();
+    try {
+      lr->ctx = ctx;
+      lr->part = part;
+      lr->prec = prec;
+      lr->nG = part->nG;
+      lr->l_max = l_max;
+      lr->eps = eps;
+      lr->kern = kern;
+      plan_aca(ctx, tree, part, lr, 0);
+      if (!lr->streamed) run_aca_stored(ctx, tree, part, kern, lr);
+    } catch (...) {
+      delete lr;
+      throw;
+    }
+    *out = lr;
   }
-  *out = lr;
   HH_API_END(ctx)
 }
 

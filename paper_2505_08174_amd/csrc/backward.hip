@@ -11,8 +11,8 @@
 //  cotangent for every kernel sample it took, and those sampled pairs are
 //  back-propagated the same way.
 // Accumulation: dX of a target row in registers, of a source row with FP64
-// atomics; dtheta per workgroup in LDS, then summed over workgroups in a fixed
-// order in FP64.
+// atomics; dtheta per workgroup in LDS (FP64 in every form), then summed over
+// workgroups in a fixed order in FP64.
 #include "api_guard.h"
 #include "devmath.h"
 #include "internal.h"
@@ -22,16 +22,16 @@ namespace {
 constexpr int TB = 256;
 inline unsigned nblk(int64_t n) { return (unsigned)((n + TB - 1) / TB); }
 
-// dtheta accumulators in LDS use the type's native LDS atomic add.
-template <class T>
-__device__ __forceinline__ void lds_add(T* p, T v) { atomicAdd(p, v); }
+// dtheta accumulates in FP64 in LDS in every form (one workgroup adds the
+// contributions of up to ~1e6 pairs per parameter).
+__device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); }
 
 // Cotangent of one kernel entry K(r) (3x3, symmetric) for the MLP kernel:
 // adds d/dtheta of sum_ab gb_ab K_ab(r) into dth (LDS, packed layout) and
 // returns d/dr.
 template <class T>
 __device__ void mlp_vjp(const T* __restrict__ P, int mode, T rx, T ry, T rz,
-                        const T gb[9], T* __restrict__ dth, T dr[3]) {
+                        const T gb[9], double* __restrict__ dth, T dr[3]) {
   const T d2 = rx * rx + ry * ry + rz * rz;
   const T id = hh_rsqrt(d2);
   T v0 = rx, v1 = ry, v2 = rz;
@@ -126,15 +126,14 @@ __device__ __forceinline__ void atomic_add3(double* p, double a, double b, doubl
 }
 
 template <class T>
-__device__ __forceinline__ void stage_params(T* wl, T* dth, const T* w) {
+__device__ __forceinline__ void stage_params(T* wl, double* dth, const T* w) {
   for (int i = threadIdx.x; i < MLP_NP; i += TB) {
     wl[i] = w[i];
     dth[i] = 0;
   }
 }
 
-template <class T>
-__device__ __forceinline__ void flush_params(const T* dth, double* part) {
+__device__ __forceinline__ void flush_params(const double* dth, double* part) {
   for (int i = threadIdx.x; i < MLP_NP; i += TB) part[(int64_t)blockIdx.x * MLP_NP + i] = dth[i];
 }
 
@@ -150,7 +149,7 @@ __global__ __launch_bounds__(TB) void k_near_vjp(const int4* __restrict__ nodes,
                                                  const T* __restrict__ wgt, int mode,
                                                  double* __restrict__ dXs, double* __restrict__ part) {
   __shared__ T wl[MLP_NP];
-  __shared__ T dth[MLP_NP];
+  __shared__ double dth[MLP_NP];
   stage_params(wl, dth, wgt);
   __syncthreads();
   const int leaf = blockIdx.x;
@@ -293,7 +292,7 @@ __global__ __launch_bounds__(TB) void k_aca_adjoint(
       //   ab(i) = cb_k(i) P^-T, ab(i_k) -= P^-T S P^-T, S = sum_i a_k(i)^T cb_k(i)
       double Pm[9], Pi[9];
       {
-        const T* P = Qp(k) + 9 * (int64_t)jk;
+        const T* P = Cp(k) + 9 * (int64_t)(c + q);   // the pivot entry the forward used
         for (int e = 0; e < 9; ++e) Pm[e] = P[e];
         double det = Pm[0] * (Pm[4] * Pm[8] - Pm[5] * Pm[7]) - Pm[1] * (Pm[3] * Pm[8] - Pm[5] * Pm[6]) +
                      Pm[2] * (Pm[3] * Pm[7] - Pm[4] * Pm[6]);
@@ -387,7 +386,7 @@ __global__ __launch_bounds__(TB) void k_far_vjp(const int2* __restrict__ G, int6
                                                 double* __restrict__ dXs,
                                                 double* __restrict__ part) {
   __shared__ T wl[MLP_NP];
-  __shared__ T dth[MLP_NP];
+  __shared__ double dth[MLP_NP];
   stage_params(wl, dth, wgt);
   __syncthreads();
   for (int64_t b = blockIdx.x; b < nG; b += gridDim.x) {
@@ -432,7 +431,7 @@ __global__ __launch_bounds__(TB) void k_fallback_bwd(const int2* __restrict__ G,
                                                      double* __restrict__ dXs,
                                                      double* __restrict__ part) {
   __shared__ T wl[KIND == KIND_MLP ? MLP_NP : 1];
-  __shared__ T dth[KIND == KIND_MLP ? MLP_NP : 1];
+  __shared__ double dth[KIND == KIND_MLP ? MLP_NP : 1];
   if (KIND == KIND_MLP) stage_params(wl, dth, (const T*)kp.w);
   __syncthreads();
   for (int64_t b = blockIdx.x; b < nG; b += gridDim.x) {
@@ -551,14 +550,7 @@ void backward_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kernel k, co
     HIP_OK(hipMemsetAsync(part.p, 0, (int64_t)nparts * MLP_NP * sizeof(double), st));
   }
   if (lr->n_fallback > 0 && (dF || mlp)) {
-    KParams kp;
-    kp.kind = k->kind;
-    kp.input_mode = k->input_mode;
-    kp.a = k->a;
-    kp.c8 = 1.0 / (8.0 * HH_PI * k->mu);
-    kp.c6 = 1.0 / (6.0 * HH_PI * k->mu * k->a);
-    kp.alpha1 = k->alpha1;
-    kp.w = sizeof(T) == 8 ? k->p64.p : k->p32.p;
+    const KParams kp = make_kparams(k, sizeof(T) == 8);
     double* fbpart = mlp ? part.as<double>() + (int64_t)(gnear + gfar) * MLP_NP : nullptr;
     if (k->kind == KIND_MLP)
       hipLaunchKernelGGL((k_fallback_bwd<T, KIND_MLP>), dim3(gfb), dim3(TB), 0, st,

@@ -5,6 +5,7 @@
 #include <new>
 
 #include "api_guard.h"
+#include "devmath.h"
 #include "internal.h"
 
 void DevBuf::release() {
@@ -78,6 +79,18 @@ static void drain_phases(hh_ctx ctx) {
 }
 
 size_t elem_size(int prec) { return prec == HH_FP64 ? 8 : 4; }
+
+KParams make_kparams(hh_kernel k, bool fp64) {
+  KParams kp;
+  kp.kind = k->kind;
+  kp.input_mode = k->input_mode;
+  kp.a = k->a;
+  kp.c8 = 1.0 / (8.0 * HH_PI * k->mu);
+  kp.c6 = 1.0 / (6.0 * HH_PI * k->mu * k->a);
+  kp.alpha1 = k->alpha1;
+  kp.w = fp64 ? k->p64.p : k->p32.p;
+  return kp;
+}
 
 namespace {
 __global__ void k_zero_words(int64_t* __restrict__ p, int64_t n) {

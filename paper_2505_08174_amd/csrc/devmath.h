@@ -147,6 +147,10 @@ struct KParams {
   const void* w;     // packed MLP parameters (double or float per T)
 };
 
+// Kernel parameters of a kernel handle, with the MLP weights of the FP64
+// (fp64) or the FP32 copy.
+KParams make_kparams(hh_kernel k, bool fp64);
+
 template <class T>
 __device__ __forceinline__ void kernel_entry(const KParams& kp, const T* __restrict__ wl, T rx,
                                              T ry, T rz, T K[9]) {

@@ -420,6 +420,21 @@ __global__ __launch_bounds__(T256) void k_roots(const int4* __restrict__ nodes, 
 
 inline unsigned nblk(int64_t n, int t = T256) { return (unsigned)((n + t - 1) / t); }
 
+// Refit: new positions in the kept order (xs[s] = X[perm[s]]).
+__global__ __launch_bounds__(T256) void k_refit_gather(const double* __restrict__ X, int64_t n,
+                                                       const int32_t* __restrict__ perm,
+                                                       double* __restrict__ xs,
+                                                       int* __restrict__ bad) {
+  int64_t s = (int64_t)blockIdx.x * T256 + threadIdx.x;
+  if (s >= n) return;
+  const int64_t o = perm[s];
+  const double x0 = X[3 * o], x1 = X[3 * o + 1], x2 = X[3 * o + 2];
+  if (!isfinite(x0) || !isfinite(x1) || !isfinite(x2)) atomicOr(bad, 1);
+  xs[3 * s] = x0;
+  xs[3 * s + 1] = x1;
+  xs[3 * s + 2] = x2;
+}
+
 }  // namespace
 
 static void build_tree_impl(hh_ctx ctx, hh_tree_s* t, const double* X, int64_t n,
@@ -605,6 +620,26 @@ hh_status hh_build_tree_batch_leaf(hh_ctx ctx, const double* X, const int64_t* o
     return HH_ERR_INVALID_ARG;
   }
   return build_batch(ctx, X, offsets, n_sys, c_leafs, 2, out);
+}
+
+hh_status hh_tree_refit(hh_ctx ctx, hh_tree tree, const double* X) {
+  HH_API_BEGIN(ctx)
+  HH_REQUIRE(tree && X, HH_ERR_INVALID_ARG, "NULL argument");
+  HH_REQUIRE(tree->ctx == ctx, HH_ERR_INVALID_ARG, "tree belongs to another context");
+  hipStream_t st = ctx->stream;
+  const int64_t n = tree->n, m = tree->n_nodes, nl = tree->n_leaves;
+  int* bad = (int*)ctx->scratch_flag.p;
+  HIP_OK(hipMemsetAsync(bad, 0, sizeof(int64_t), st));
+  hipLaunchKernelGGL(k_refit_gather, dim3(nblk(n)), dim3(T256), 0, st, X, n,
+                     tree->perm.as<int32_t>(), tree->xs.as<double>(), bad);
+  hipLaunchKernelGGL(k_leaf_box, dim3(nblk(nl * 64)), dim3(T256), 0, st,
+                     tree->leaves.as<int32_t>(), nl, tree->nodes.as<int4>(), tree->xs.as<double>(),
+                     tree->leaf_of.as<int32_t>(), tree->bbox.as<double>());
+  hipLaunchKernelGGL(k_inner_box, dim3(nblk(m * 64)), dim3(T256), 0, st, tree->nodes.as<int4>(),
+                     m, tree->leaves.as<int32_t>(), nl, tree->bbox.as<double>());
+  HIP_OK(hipGetLastError());
+  HH_REQUIRE(read_i64(ctx, bad) == 0, HH_ERR_INVALID_ARG, "X holds a non-finite coordinate");
+  HH_API_END(ctx)
 }
 
 void hh_tree_free(hh_tree t) { delete t; }
