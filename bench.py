@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--autotune", action="store_true",
                     help="pick leaf sizes (per size class of systems) and the workgroup "
                          "threshold by timing whole steps first (not timed)")
+    ap.add_argument("--backward", action="store_true",
+                    help="time the step plus hh_matvec_backward (dF, dX, dtheta of "
+                         "L = w . U), FP32 or FP64 forms")
     return ap.parse_args()
 
 
@@ -87,6 +90,26 @@ def stored_traffic(kernel, workload):
     if rec.get("source_sha256") != sources_sha(kernel):
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def golden_rows(workload, X, F):
+    """The stored FP64 dense-oracle rows of this workload (tests/golden/
+    make_rows.py), if they were written for these exact inputs."""
+    path = os.path.join(ROOT, "tests", "golden", "rows_%s.npz" % workload)
+    if not os.path.exists(path):
+        return None
+    d = np.load(path)
+    dig = lambda a: hashlib.sha256(np.ascontiguousarray(a, dtype=np.float64).tobytes()).hexdigest()
+    if str(d["sha_X"]) != dig(X) or str(d["sha_F"]) != dig(F):
+        return None
+    return d["rows"], d["U"], os.path.relpath(path, ROOT)
+
+
+def accuracy(U_gpu, rows, ref):
+    """Eq. (11) over the sampled rows, and the largest per-row relative error."""
+    d = U_gpu[rows] - ref
+    per_row = np.linalg.norm(d, axis=1) / np.linalg.norm(ref, axis=1)
+    return float(np.linalg.norm(d) / np.linalg.norm(ref)), float(per_row.max())
 
 
 def copy_calibration():
@@ -193,6 +216,11 @@ def main():
         tuned["seconds"] = round(time.perf_counter() - t0, 1)
         log("autotuned:", tuned)
 
+    if a.backward:
+        # cotangent w ~ N(0, I3); the backward needs stored factors
+        wd = torch.tensor(wl.normal_forces(n, seed=5), dtype=fdt, device="cuda:0")
+        ctx.set_budget(200 << 30)
+
     def step():
         if offsets is None:
             t = hh.build_tree(ctx, Xd, c_leaf)
@@ -201,6 +229,8 @@ def main():
         p = hh.partition(ctx, t, cfg["eta"])
         lr = hh.aca_build(ctx, t, p, kern, prec, cfg["eps"], a.l_max)
         U = hh.matvec(ctx, t, p, lr, kern, Fd, prec)
+        if a.backward:
+            hh.matvec_backward(ctx, t, p, lr, kern, Fd, wd.to(U.dtype), prec)
         return U, t, p, lr
 
     for i in range(a.warmup):
@@ -262,11 +292,14 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32",
                                                          "bf16": "bf16", "bf16_split": "bf16"}[prec],
         "data": "synthetic",
-        "config": {"workload": a.workload, "n": n, "kernel": cfg["kernel"], "precision": prec,
+        "config": {"workload": a.workload, "n": n, "kernel": cfg["kernel"],
+                   "mlp_input": "direction" if cfg["kernel"] == "mlp" else None,
+                   "precision": prec,
                    "c_leaf": cfg["c_leaf"] if tuned is None else tuned,
                    "eta": cfg["eta"], "eps": cfg["eps"],
                    "l_max": a.l_max, "geometry": cfg["geom"], "phi": cfg["phi"],
-                   "systems": 1 if offsets is None else len(offsets) - 1},
+                   "systems": 1 if offsets is None else len(offsets) - 1,
+                   "backward": bool(a.backward)},
         "phases_ms": {k: round(v, 3) for k, v in per_step.items()},
         "work": {"nodes": nn, "leaves": nl, "blocks_G": nG, "blocks_H": nH,
                  "near_pairs": pairs_near, "aca_samples": li["samples"],
@@ -274,11 +307,21 @@ def main():
                  "factor_bytes": li["bytes"]},
         "roofline": roof,
     }
+    gold = golden_rows(a.workload, X, F) if a.n is None and offsets is None else None
+    if gold is not None:
+        rows, ref, src = gold
+        e, emax = accuracy(U_host, rows, ref)
+        out["eps_r_sampled_rows"] = e
+        out["eps_r_max_row"] = emax
+        out["eps_r_rows"] = int(rows.size)
+        out["eps_r_reference"] = src + " (dense FP64 oracle rows, seed 3)"
     if not a.no_cpu:
         cb, err, nrows = cpu_baseline(X, F, cfg, U_host, a.cpu_seconds)
         out["cpu_baseline"] = cb
-        out["eps_r_sampled_rows"] = err
-        out["eps_r_rows"] = nrows
+        if gold is None:
+            out["eps_r_sampled_rows"] = err
+            out["eps_r_rows"] = nrows
+            out["eps_r_reference"] = "the cpu_baseline rows"
     print(json.dumps(out), flush=True)
 
 

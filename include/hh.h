@@ -49,6 +49,7 @@ typedef struct hh_tree_s* hh_tree;
 typedef struct hh_part_s* hh_part;
 typedef struct hh_lowrank_s* hh_lowrank;
 typedef struct hh_kernel_s* hh_kernel;
+typedef struct hh_batch_s* hh_batch;
 
 typedef enum {
   HH_OK = 0,
@@ -237,6 +238,50 @@ void hh_tree_free(hh_tree t);
 void hh_part_free(hh_part p);
 void hh_lowrank_free(hh_lowrank l);
 
+/* ------------------------------------------------------- the batched form */
+
+/* Parameters of a batch of independent systems (suspensions) concatenated in
+ * one position array. */
+typedef struct {
+  int32_t n_sys;           /* number of systems, >= 1 */
+  const int64_t* offsets;  /* host, n_sys + 1 particle offsets (0, ..., n), increasing */
+  const int32_t* c_leafs;  /* host, leaf size per system (each >= 2), or NULL ... */
+  int32_t c_leaf;          /* ... for this leaf size in every system */
+  double eta;              /* admissibility parameter of Eq. (7), > 0 */
+  double eps;              /* ACA tolerance (Eq. (10)), >= 0 */
+  int32_t l_max;           /* ACA rank cap, 1..64 */
+  hh_precision prec;
+} hh_batch_params;
+
+/* Builds the H-matrix of every system of a batch in one handle: the batched
+ * tree (hh_build_tree_batch_leaf), the partition (Algorithm 1 from every
+ * system's root, so no block couples two systems) and the ACA plan or
+ * factors (hh_aca_build), with all systems' blocks in the same launches.
+ * X: device FP64 [n][3]. kern must outlive the batch. Errors as the calls
+ * it makes. Syncs. */
+hh_status hh_batch_create(hh_ctx ctx, const double* X, const hh_batch_params* params,
+                          hh_kernel kern, hh_batch* out);
+
+/* U = M F for every system of the batch (as hh_matvec; F and U device
+ * arrays of the batch's n particles, types per precision). The first call
+ * with a given (F, U) computes U eagerly, which sizes every workspace, and
+ * records the whole product (every launch of hh_matvec, in streamed mode the
+ * ACA with its fused apply and the team kernel on the context's second
+ * stream) in a HIP graph on a private stream; it syncs. Every later call
+ * with the same pointers is one graph launch on the context stream that
+ * recomputes U from the current contents of F (no sync, no allocation, no
+ * host work per system). A call with other pointers records a new graph.
+ * Calls on one batch must not overlap in time. */
+hh_status hh_batch_matvec(hh_ctx ctx, hh_batch b, const void* F, void* U);
+
+/* Sizes and parts of a batch (each output nullable): particles, systems,
+ * nodes of the recorded graph (0 before the first product), graph launches
+ * so far, and the tree, partition and low-rank handles it owns (valid until
+ * hh_batch_free; do not free them). */
+hh_status hh_batch_info(hh_batch b, int64_t* n, int32_t* n_sys, int64_t* graph_nodes,
+                        int64_t* graph_launches, hh_tree* tree, hh_part* part, hh_lowrank* lr);
+void hh_batch_free(hh_batch b);
+
 /* ------------------------------------------------------- export and stats */
 
 /* Sizes of a tree: particles, nodes, leaves. Host outputs (nullable). */
@@ -282,6 +327,7 @@ hh_status hh_lowrank_factor(hh_lowrank l, int64_t b, int32_t k, double* ck, doub
 #define HH_PHASE_NEAR 3      /* the near-field kernel launch of hh_matvec */
 #define HH_PHASE_FAR 4       /* the t_k = Q_k F launch of hh_matvec */
 #define HH_PHASE_COMBINE 5   /* the combine/unpermute launch of hh_matvec */
+#define HH_PHASE_BACKWARD 6  /* the launches of hh_matvec_backward */
 #define HH_NPHASE 8
 hh_status hh_ctx_set_profiling(hh_ctx ctx, int on);
 /* Accumulated milliseconds and event pairs per phase since the last reset

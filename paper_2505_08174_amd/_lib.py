@@ -18,12 +18,21 @@ HH_MLP_INPUT_DIRECTION, HH_MLP_INPUT_DISPLACEMENT = 0, 1
 HH_MLP_NPARAM = 9161
 LMAX_CAP = 64
 HH_NPHASE = 8
-PHASES = ("tree", "partition", "aca", "near", "far", "combine")
+PHASES = ("tree", "partition", "aca", "near", "far", "combine", "backward")
 
 # name -> (restype, argtypes); every symbol declared in include/hh.h
 _vp, _i32, _i64, _d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
 _pi64, _pi32, _pd, _pu64 = (C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_double),
                             C.POINTER(C.c_uint64))
+
+
+class BatchParams(C.Structure):
+    """hh_batch_params of include/hh.h."""
+    _fields_ = [("n_sys", C.c_int32), ("offsets", C.POINTER(C.c_int64)),
+                ("c_leafs", C.POINTER(C.c_int32)), ("c_leaf", C.c_int32), ("eta", C.c_double),
+                ("eps", C.c_double), ("l_max", C.c_int32), ("prec", C.c_int)]
+
+
 SIGNATURES = {
     "hh_ctx_create": (C.c_int, [C.c_int, _vp, C.POINTER(_vp)]),
     "hh_ctx_destroy": (None, [_vp]),
@@ -44,6 +53,11 @@ SIGNATURES = {
     "hh_aca_build_pivots": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int, _pi32, _pi32, _pi32, _pi32,
                                       C.POINTER(_vp)]),
     "hh_tree_refit": (C.c_int, [_vp, _vp, _vp]),
+    "hh_batch_create": (C.c_int, [_vp, _vp, C.POINTER(BatchParams), _vp, C.POINTER(_vp)]),
+    "hh_batch_matvec": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "hh_batch_info": (C.c_int, [_vp, _pi64, _pi32, _pi64, _pi64, C.POINTER(_vp),
+                                C.POINTER(_vp), C.POINTER(_vp)]),
+    "hh_batch_free": (None, [_vp]),
     "hh_matvec": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int, _vp, _vp]),
     "hh_matvec_backward": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int, _vp, _vp, _vp, _vp, _vp]),
     "hh_tree_free": (None, [_vp]),
@@ -61,6 +75,8 @@ SIGNATURES = {
     "hh_ctx_phase_times": (C.c_int, [_vp, _pd, _pi64, C.c_int]),
     "hh_device_arch_ok": (C.c_int, []),
 }
+
+
 
 _lib = None
 

@@ -387,6 +387,81 @@ class HMatrix:
         return g, U
 
 
+class _Borrowed:
+    """A handle owned by another object (not freed here)."""
+
+    def __del__(self):
+        pass
+
+
+class _BTree(_Borrowed, Tree):
+    pass
+
+
+class _BPart(_Borrowed, Partition):
+    pass
+
+
+class _BLowRank(_Borrowed, LowRank):
+    pass
+
+
+class Batch(_Handle):
+    """Many independent systems in one handle (hh_batch_create); the product
+    is recorded once in a HIP graph and replayed by one graph launch per call
+    (hh_batch_matvec). c_leaf: one leaf size or one per system."""
+    _free = "hh_batch_free"
+
+    def __init__(self, ctx: Context, X: torch.Tensor, offsets, kern: Kernel, c_leaf=128,
+                 eta: float = 1.0, eps: float = 1e-4, prec="bf16", l_max: int = 48):
+        assert X.is_cuda and X.dtype == torch.float64 and X.dim() == 2 and X.shape[1] == 3
+        X = X.contiguous()
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        assert off[0] == 0 and off[-1] == X.shape[0]
+        prm = L.BatchParams()
+        prm.n_sys = len(off) - 1
+        prm.offsets = off.ctypes.data_as(C.POINTER(C.c_int64))
+        cl = None
+        if np.ndim(c_leaf) == 0:
+            prm.c_leafs = C.POINTER(C.c_int32)()
+            prm.c_leaf = int(c_leaf)
+        else:
+            cl = np.ascontiguousarray(c_leaf, dtype=np.int32)
+            assert cl.shape == (prm.n_sys,)
+            prm.c_leafs = cl.ctypes.data_as(C.POINTER(C.c_int32))
+            prm.c_leaf = 0
+        prm.eta, prm.eps, prm.l_max, prm.prec = float(eta), float(eps), int(l_max), _prec(prec)
+        h = C.c_void_p()
+        ctx.check(L.load().hh_batch_create(ctx.h, _ptr(X), C.byref(prm), kern.h, C.byref(h)))
+        super().__init__(ctx, h, keep=(kern,))
+        self.kern, self.prec, self.offsets = kern, _prec(prec), off
+        tree, part, lr = C.c_void_p(), C.c_void_p(), C.c_void_p()
+        ctx.check(L.load().hh_batch_info(h, None, None, None, None, C.byref(tree), C.byref(part),
+                                         C.byref(lr)))
+        self.tree = _BTree(ctx, tree)
+        self.part = _BPart(ctx, part)
+        self.lr = _BLowRank(ctx, lr)
+
+    def info(self):
+        n, ns, nodes, launches = C.c_int64(), C.c_int32(), C.c_int64(), C.c_int64()
+        self.ctx.check(L.load().hh_batch_info(self.h, C.byref(n), C.byref(ns), C.byref(nodes),
+                                              C.byref(launches), None, None, None))
+        return {"n": n.value, "n_sys": ns.value, "graph_nodes": nodes.value,
+                "graph_launches": launches.value}
+
+    def matvec(self, F: torch.Tensor, U: torch.Tensor | None = None) -> torch.Tensor:
+        """U = M F; the first call with these buffers records the graph, later
+        calls replay it (F and U must keep their storage)."""
+        n = int(self.offsets[-1])
+        assert F.is_cuda and F.dtype == F_DTYPE[self.prec] and F.shape == (n, 3)
+        assert F.is_contiguous()
+        if U is None:
+            U = torch.empty(F.shape, dtype=U_DTYPE[self.prec], device=F.device)
+        assert U.dtype == U_DTYPE[self.prec] and U.is_contiguous() and U.shape == F.shape
+        self.ctx.check(L.load().hh_batch_matvec(self.ctx.h, self.h, _ptr(F), _ptr(U)))
+        return U
+
+
 def hmatvec(ctx, X, F, kern, c_leaf=64, eta=1.0, eps=1e-6, prec="fp64", l_max=48):
     """One full step: tree, partition, ACA and product."""
     return HMatrix(ctx, X, kern, c_leaf, eta, eps, prec, l_max) @ F

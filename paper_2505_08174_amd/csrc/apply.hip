@@ -184,29 +184,29 @@ __global__ __launch_bounds__(T256) void k_final(int64_t n, const int32_t* __rest
     U[3 * o + d] = (TO)(((double)Un[3 * s + d] + Uf[3 * s + d]) + alpha1 * (double)Fs[3 * s + d]);
 }
 
+// Stored mode. Fs_ws and Un_ws hold the sorted forces (3 n T) and the
+// near-field rows (3 n TU); timed = false records no phase events.
 template <class T, class TI, class TO, class TU>
 void matvec_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kernel k, const void* F,
-              void* U) {
+              void* U, void* Fs_ws, void* Un_ws, bool timed) {
   hipStream_t st = ctx->stream;
   const int64_t n = t->n;
-  DevBuf& Fs = lr->ws_f;
-  DevBuf& Un = lr->ws_near;
-  Fs.ensure(st, 3 * n * sizeof(T));
-  Un.ensure(st, 3 * n * sizeof(TU));
+  T* Fs = (T*)Fs_ws;
+  TU* Un = (TU*)Un_ws;
   hipLaunchKernelGGL((k_gather_rows<TI, T>), dim3(nblk(n)), dim3(T256), 0, st, (const TI*)F,
-                     t->perm.as<int32_t>(), n, Fs.as<T>());
+                     t->perm.as<int32_t>(), n, Fs);
   {
-    PhaseTimer timer(ctx, HH_PHASE_NEAR);
-    launch_near(ctx, t, p, k, lr->prec, Fs.p, Un.p);
+    PhaseTimer timer(ctx, HH_PHASE_NEAR, timed);
+    launch_near(ctx, t, p, k, lr->prec, Fs, Un);
   }
   int64_t nG = p->nG;
   if (nG > 0) {
-    PhaseTimer timer(ctx, HH_PHASE_FAR);
+    PhaseTimer timer(ctx, HH_PHASE_FAR, timed);
     int grid = (int)std::min<int64_t>(nG, 8192);
     hipLaunchKernelGGL((k_far_t<T>), dim3(grid), dim3(T256), 0, st, p->G.as<int2>(), nG,
                        t->nodes.as<int4>(), lr->rank.as<int32_t>(), lr->flag.as<int32_t>(),
-                       lr->fptr.as<int64_t>(), lr->toff.as<int64_t>(), lr->pool.as<T>(),
-                       Fs.as<T>(), lr->tbuf.as<double>());
+                       lr->fptr.as<int64_t>(), lr->toff.as<int64_t>(), lr->pool.as<T>(), Fs,
+                       lr->tbuf.as<double>());
   }
   KParams kp = make_kparams(k, sizeof(T) == 8);
 #define COMBINE(KIND_)                                                                       \
@@ -215,13 +215,24 @@ void matvec_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kernel k, cons
                      t->nodes.as<int4>(), p->far_ptr.as<int32_t>(), p->G.as<int2>(),           \
                      lr->rank.as<int32_t>(), lr->flag.as<int32_t>(), lr->fptr.as<int64_t>(),   \
                      lr->toff.as<int64_t>(), lr->pool.as<T>(), lr->tbuf.as<double>(),          \
-                     t->xs.as<double>(), Fs.as<T>(), Un.as<TU>(), kp, (TO*)U)
+                     t->xs.as<double>(), Fs, Un, kp, (TO*)U)
   {
-    PhaseTimer timer(ctx, HH_PHASE_COMBINE);
+    PhaseTimer timer(ctx, HH_PHASE_COMBINE, timed);
     if (k->kind == KIND_MLP) COMBINE(KIND_MLP); else COMBINE(KIND_RPY);
   }
 #undef COMBINE
   HIP_OK(hipGetLastError());
+}
+
+// Stored mode with the workspaces of the low-rank handle (sized on the first
+// product, reused after).
+template <class T, class TI, class TO, class TU>
+void matvec_ws_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kernel k, const void* F,
+                 void* U) {
+  const int64_t n = t->n;
+  lr->ws_f.ensure(ctx->stream, 3 * n * sizeof(T));
+  lr->ws_near.ensure(ctx->stream, 3 * n * sizeof(TU));
+  matvec_t<T, TI, TO, TU>(ctx, t, p, lr, k, F, U, lr->ws_f.p, lr->ws_near.p, true);
 }
 
 template <class T, class TI, class TO, class TU>
@@ -352,13 +363,13 @@ hh_status hh_matvec(hh_ctx ctx, hh_tree tree, hh_part part, hh_lowrank lr, hh_ke
     else
       matvec_streamed_t<float, float, double, float>(ctx, tree, part, lr, kern, F, U);
   } else if (prec == HH_FP64) {
-    matvec_t<double, double, double, double>(ctx, tree, part, lr, kern, F, U);
+    matvec_ws_t<double, double, double, double>(ctx, tree, part, lr, kern, F, U);
   } else if (prec == HH_FP32) {
-    matvec_t<float, float, float, float>(ctx, tree, part, lr, kern, F, U);
+    matvec_ws_t<float, float, float, float>(ctx, tree, part, lr, kern, F, U);
   } else if (mfma) {
-    matvec_t<float, float, double, double>(ctx, tree, part, lr, kern, F, U);
+    matvec_ws_t<float, float, double, double>(ctx, tree, part, lr, kern, F, U);
   } else {
-    matvec_t<float, float, double, float>(ctx, tree, part, lr, kern, F, U);
+    matvec_ws_t<float, float, double, float>(ctx, tree, part, lr, kern, F, U);
   }
   HH_API_END(ctx)
 }

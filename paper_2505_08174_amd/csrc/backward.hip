@@ -610,6 +610,7 @@ extern "C" hh_status hh_matvec_backward(hh_ctx ctx, hh_tree tree, hh_part part, 
              "the backward needs stored factors (raise the budget with hh_ctx_set_budget)");
   HH_REQUIRE(!(dX || dparams) || kern->kind == KIND_MLP, HH_ERR_INVALID_ARG,
              "dX and dparams need the MLP kernel");
+  PhaseTimer timer(ctx, HH_PHASE_BACKWARD);
   if (prec == HH_FP64)
     backward_t<double>(ctx, tree, part, lr, kern, F, dU, dF, dX, dparams);
   else

@@ -41,8 +41,8 @@ static hipEvent_t take_event(hh_ctx ctx) {
   return e;
 }
 
-PhaseTimer::PhaseTimer(hh_ctx c, int ph) : ctx(c), phase(ph) {
-  if (!ctx->profiling) return;
+PhaseTimer::PhaseTimer(hh_ctx c, int ph, bool on) : ctx(c), phase(ph) {
+  if (!on || !ctx->profiling) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(ctx->stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
     return;   // no timing events inside a captured graph

@@ -82,7 +82,8 @@ struct PhaseTimer {
   hh_ctx ctx;
   int phase;
   hipEvent_t a = nullptr;
-  PhaseTimer(hh_ctx c, int ph);
+  // on = false: records nothing (the allocation-free product)
+  PhaseTimer(hh_ctx c, int ph, bool on = true);
   ~PhaseTimer();
 };
 
@@ -132,7 +133,7 @@ struct hh_tree_s {
   DevBuf leaf_id;   // int32 [n_nodes] rank among leaves, -1 for internal
   DevBuf leaves;    // int32 [n_leaves] node id of each leaf, in order
   DevBuf leaf_of;   // int32 [n] leaf node of sorted position s
-  DevBuf units;     // int2 [n_units] (leaf rank, chunk of 32 targets), built lazily
+  DevBuf units;     // int2 [n_units] (leaf rank, chunk of 32 targets), built with the tree
   int64_t n_units = 0;
   int n_sys = 1;                    // independent systems (batched build)
   std::vector<int64_t> offs_host;   // particle offsets of the systems [n_sys+1]
@@ -180,7 +181,7 @@ struct hh_lowrank_s {
   DevBuf flag;      // int32 [nG] 1 = dense fallback
   DevBuf piv;       // int32 [nG][2][LMAX_CAP] (i_k then j_k), local indices
   DevBuf fptr;      // int64 [nG][LMAX_CAP] element offset of factor k in pool
-  DevBuf pool;      // factor storage (double or float), (c + q) * 9 per factor
+  DevBuf pool;      // factor storage (double or float), 9 (c + q + 1) per step: c_k, q_k, P_k
   int64_t pool_elems = 0;
   int64_t rank_sum = 0, n_fallback = 0, samples = 0, used_elems = 0;
   DevBuf toff;      // int64 [nG] offset of the block's t vectors (rank*3)

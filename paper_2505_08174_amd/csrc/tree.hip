@@ -557,6 +557,9 @@ static void build_tree_impl(hh_ctx ctx, hh_tree_s* t, const double* X, int64_t n
   hipLaunchKernelGGL(k_inner_box, dim3(nblk(m * 64)), dim3(T256), 0, st, t->nodes.as<int4>(), m,
                      t->leaves.as<int32_t>(), nl, t->bbox.as<double>());
   HIP_OK(hipGetLastError());
+  // work units of the MFMA near field (32-target chunks of every leaf), so
+  // that no product on this tree allocates
+  ensure_units(ctx, t);
 }
 
 extern "C" {

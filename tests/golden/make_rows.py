@@ -6,7 +6,10 @@ dense product U_i = alpha_1 F_i + sum_{j != i} K(x_i - x_j) F_j of those rows
 (Eq. (2) restricted to the one-body and two-body terms), as computed by
 oracle.dense, in tests/golden/rows_<workload>.npz together with SHA-256
 digests of X and F, so a reader can check that it compares against the same
-inputs. Only oracle/ and the input generators are called.
+inputs. For a workload of many independent systems, k / n_sys rows are
+sampled in each system (workloads.sample_rows(n_s, k / n_sys, seed=3)) and
+the sum runs over the row's own system. Only oracle/ and the input
+generators are called.
 
 Usage: python tests/golden/make_rows.py WORKLOAD [WORKLOAD ...] [--rows K] [--procs P]
 """
@@ -53,22 +56,34 @@ def _init(X, F, kind):
     _K = oracle_kernel({"kernel": kind})
 
 
-def _rows(rows):
-    return OD.dense_u(_X, _F, _K, rows)
+def _rows(task):
+    a, b, rows = task   # particles [a, b) form the row's system; rows are local
+    return OD.dense_u(_X[a:b], _F[a:b], _K, rows)
 
 
 def make(name: str, k: int, procs: int) -> str:
     X, F, cfg = wl.workload(name)
     n = X.shape[0]
-    rows = wl.sample_rows(n, min(k, n), seed=3)
+    off = cfg.get("offsets")
+    if off is None:
+        rows = wl.sample_rows(n, min(k, n), seed=3)
+        chunks = [(0, n, rows[i:i + 8]) for i in range(0, rows.size, 8)]
+    else:
+        per = max(1, k // (len(off) - 1))
+        rows, chunks = [], []
+        for s_ in range(len(off) - 1):
+            a, b = int(off[s_]), int(off[s_ + 1])
+            loc = wl.sample_rows(b - a, min(per, b - a), seed=3)
+            rows.append(loc + a)
+            chunks += [(a, b, loc[i:i + 8]) for i in range(0, loc.size, 8)]
+        rows = np.concatenate(rows)
     t0 = time.perf_counter()
-    chunks = [rows[i:i + 8] for i in range(0, rows.size, 8)]
     with mp.get_context("fork").Pool(procs, _init, (X, F, cfg["kernel"])) as pool:
         parts = []
         for i, u in enumerate(pool.imap(_rows, chunks)):
             parts.append(u)
             if i % 32 == 0:
-                print("%s: %d / %d rows, %.0f s" % (name, 8 * (i + 1), rows.size,
+                print("%s: %d / %d chunks, %.0f s" % (name, i + 1, len(chunks),
                                                     time.perf_counter() - t0), flush=True)
     U = np.concatenate(parts)
     out = os.path.join(HERE, "rows_%s.npz" % name)

@@ -244,16 +244,21 @@ def test_backward_finite_differences_frozen_5k():
     tree, partition, pivots and fallbacks stay those of the unperturbed
     build (hh_tree_refit, freeze_pivots_from). Each coordinate within 1e-6 of
     the largest gradient entry of its kind (FD truncation ~h^2, rounding of
-    L ~1e-16 |L| / h)."""
+    L ~1e-16 |L| / h). The pivots are those of the |det| search (an FP32
+    build) replayed in FP64: the largest-Frobenius pivots of the FP64 search
+    can be nearly singular 3x3 entries for this indefinite kernel, and a
+    perturbation of theta moves every entry, so P^-1 would change faster than
+    a difference step resolves."""
     from gpu_common import ctx, dev, kernels, mlp_params, say
     X, F, cfg = wl.workload("diff_5k")
     n = X.shape[0]
     w = wl.normal_forces(n, seed=5)
     _, kg = kernels("mlp")
     theta = hh.pack_mlp(mlp_params())
-    hm = hh.HMatrix(ctx(), dev(X), kg, c_leaf=cfg["c_leaf"], eta=1.0, eps=cfg["eps"], prec="fp64")
+    hm = hh.HMatrix(ctx(), dev(X), kg, c_leaf=cfg["c_leaf"], eta=1.0, eps=cfg["eps"], prec="fp32")
+    lr0 = hh.aca_build(ctx(), hm.tree, hm.part, kg, "fp64", freeze_pivots_from=hm.lr)
     Fd, wd = dev(F), dev(w)
-    dF, dX, dth = hh.matvec_backward(ctx(), hm.tree, hm.part, hm.lr, kg, Fd, wd, "fp64")
+    dF, dX, dth = hh.matvec_backward(ctx(), hm.tree, hm.part, lr0, kg, Fd, wd, "fp64")
     dF, dX, dth = dF.cpu().numpy(), dX.cpu().numpy(), dth.cpu().numpy()
 
     def loss(lr, kern, Fv=Fd):
@@ -264,7 +269,7 @@ def test_backward_finite_differences_frozen_5k():
     rng = wl.Rng(4, "fd")
     pts = (rng.raw(64) % (3 * n)).astype(np.int64)
     worst = {"X": 0.0, "F": 0.0, "theta": 0.0}
-    say("fd: backward done, blocks", hm.lr.info())
+    say("fd: backward done, blocks", lr0.info())
     for a_, p in enumerate(pts):
         if a_ % 16 == 0:
             say("fd X", a_)
@@ -274,7 +279,7 @@ def test_backward_finite_differences_frozen_5k():
             Xp = X.copy()
             Xp[i, d] += sgn * h
             hh.tree_refit(ctx(), hm.tree, dev(Xp))
-            lr = hh.aca_build(ctx(), hm.tree, hm.part, kg, "fp64", freeze_pivots_from=hm.lr)
+            lr = hh.aca_build(ctx(), hm.tree, hm.part, kg, "fp64", freeze_pivots_from=lr0)
             vals.append(loss(lr, kg))
         fd = (vals[0] - vals[1]) / (2 * h)
         worst["X"] = max(worst["X"], abs(fd - dX[i, d]) / np.max(np.abs(dX)))
@@ -285,7 +290,7 @@ def test_backward_finite_differences_frozen_5k():
         for sgn in (1.0, -1.0):
             Fp = F.copy()
             Fp[i, d] += sgn * h
-            vals.append(loss(hm.lr, kg, dev(Fp)))
+            vals.append(loss(lr0, kg, dev(Fp)))
         fd = (vals[0] - vals[1]) / (2 * h)
         worst["F"] = max(worst["F"], abs(fd - dF[i, d]) / np.max(np.abs(dF)))
     say("fd F done", worst)
@@ -298,7 +303,7 @@ def test_backward_finite_differences_frozen_5k():
             th = theta.copy()
             th[p] += sgn * h
             k2 = hh.Kernel.mlp(ctx(), th, "direction")
-            lr = hh.aca_build(ctx(), hm.tree, hm.part, k2, "fp64", freeze_pivots_from=hm.lr)
+            lr = hh.aca_build(ctx(), hm.tree, hm.part, k2, "fp64", freeze_pivots_from=lr0)
             vals.append(loss(lr, k2))
         fd = (vals[0] - vals[1]) / (2 * h)
         worst["theta"] = max(worst["theta"], abs(fd - dth[p]) / np.max(np.abs(dth)))
@@ -315,7 +320,7 @@ def test_backward_sampled_rows_200k():
     n = X.shape[0]
     w = wl.normal_forces(n, seed=5)
     ko, kg = kernels("mlp")
-    ctx().set_budget(160 << 30)   # stored factors (the backward needs them)
+    ctx().set_budget(250 << 30)   # stored factors (the backward needs them)
     try:
         hm = hh.HMatrix(ctx(), dev(X), kg, c_leaf=cfg["c_leaf"], eta=1.0, eps=cfg["eps"],
                         prec="fp32")
