@@ -233,17 +233,18 @@ def main():
             hh.matvec_backward(ctx, t, p, lr, kern, Fd, wd.to(U.dtype), prec)
         return U, t, p, lr
 
+    t_start = time.perf_counter()
     for i in range(a.warmup):
         U, t, p, lr = step()
         torch.cuda.synchronize()
-        log("warmup %d done" % i)
+        log("warmup %d done, %.2f s" % (i, time.perf_counter() - t_start))
     ctx.set_profiling(True)
     ctx.phase_times(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(a.steps):
         U, t, p, lr = step()
-        log("step %d enqueued" % i)
+        log("step %d enqueued, %.2f s" % (i, time.perf_counter() - t_start))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ph = ctx.phase_times(reset=True)

@@ -229,7 +229,10 @@ hh_status hh_matvec(hh_ctx ctx, hh_tree tree, hh_part part, hh_lowrank lr, hh_ke
  *       cross approximation as the function of X it is).
  *   dparams (device FP64 [HH_MLP_NPARAM], nullable, MLP kernel only):
  *       d L / d theta, accumulated into (not overwritten).
- * F and dU as in hh_matvec. Precision HH_FP64 or HH_FP32. Does not sync. */
+ * F and dU as in hh_matvec. Precision HH_FP64 or HH_FP32; stored factors
+ * only. The cotangents of the sampled kernel entries are kept for chunks of
+ * consecutive blocks of at most 2^28 values (1 GiB in FP32) at a time. Syncs
+ * (reads back the ranks to plan those chunks). */
 hh_status hh_matvec_backward(hh_ctx ctx, hh_tree tree, hh_part part, hh_lowrank lr,
                              hh_kernel kern, hh_precision prec, const void* F, const void* dU,
                              void* dF, double* dX, double* dparams);

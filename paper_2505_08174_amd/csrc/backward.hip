@@ -17,10 +17,15 @@
 #include "devmath.h"
 #include "internal.h"
 
+void block_sizes(hh_ctx ctx, hh_tree t, hh_part p, std::vector<int32_t>& cs,
+                 std::vector<int32_t>& qs);
+
 namespace {
 
 constexpr int TB = 256;
 inline unsigned nblk(int64_t n) { return (unsigned)((n + TB - 1) / TB); }
+// cotangent-pool elements per chunk of blocks (1 GiB in FP32)
+constexpr int64_t GPOOL_CHUNK = 256ll << 20;
 
 // dtheta accumulates in FP64 in LDS in every form (one workgroup adds the
 // contributions of up to ~1e6 pairs per parameter).
@@ -133,8 +138,9 @@ __device__ __forceinline__ void stage_params(T* wl, double* dth, const T* w) {
   }
 }
 
+// adds (launches in turn may share a slot; slots start at zero)
 __device__ __forceinline__ void flush_params(const double* dth, double* part) {
-  for (int i = threadIdx.x; i < MLP_NP; i += TB) part[(int64_t)blockIdx.x * MLP_NP + i] = dth[i];
+  for (int i = threadIdx.x; i < MLP_NP; i += TB) part[(int64_t)blockIdx.x * MLP_NP + i] += dth[i];
 }
 
 // Near pairs: one workgroup per target leaf, thread per target i (as the
@@ -180,16 +186,17 @@ __global__ __launch_bounds__(TB) void k_near_vjp(const int4* __restrict__ nodes,
   flush_params(dth, part);
 }
 
-// Reverse of the ACA recursion of one admissible block per workgroup.
-// Writes the cotangents of the sampled columns (in the c_k slots) and rows
-// (in the q_k slots) of the cotangent pool, and adds Q^T (C^T w) to dFs.
+// Reverse of the ACA recursion of one admissible block per workgroup, for
+// the blocks [b0, b1). Writes the cotangents of the sampled columns and rows
+// of block b into the cotangent pool at goff[b] (term k: 9 (c + q) values,
+// column then row), and adds Q^T (C^T w) to dFs.
 template <class T>
 __global__ __launch_bounds__(TB) void k_aca_adjoint(
-    const int2* __restrict__ G, int64_t nG, const int4* __restrict__ nodes,
+    const int2* __restrict__ G, int64_t b0, int64_t b1, const int4* __restrict__ nodes,
     const int32_t* __restrict__ rank, const int32_t* __restrict__ flag,
     const int32_t* __restrict__ piv, const int64_t* __restrict__ fptr,
-    const T* __restrict__ pool, T* __restrict__ gpool, const T* __restrict__ Fs,
-    const T* __restrict__ ws, double* __restrict__ dFs) {
+    const int64_t* __restrict__ goff, const T* __restrict__ pool, T* __restrict__ gpool,
+    const T* __restrict__ Fs, const T* __restrict__ ws, double* __restrict__ dFs) {
   __shared__ double s_t[LMAX_CAP][3], s_tb[LMAX_CAP][3];
   __shared__ double red[TB / 64][9];
   __shared__ double s_M[9];
@@ -208,7 +215,7 @@ __global__ __launch_bounds__(TB) void k_aca_adjoint(
     }
     __syncthreads();
   };
-  for (int64_t b = blockIdx.x; b < nG; b += gridDim.x) {
+  for (int64_t b = b0 + blockIdx.x; b < b1; b += gridDim.x) {
     if (flag[b] || rank[b] == 0) continue;
     const int2 g = G[b];
     const int4 nt = nodes[g.x], ns = nodes[g.y];
@@ -217,8 +224,8 @@ __global__ __launch_bounds__(TB) void k_aca_adjoint(
     const int32_t* pj = pi + LMAX_CAP;
     auto Cp = [&](int k) { return pool + fptr[b * LMAX_CAP + k]; };
     auto Qp = [&](int k) { return pool + fptr[b * LMAX_CAP + k] + 9 * (int64_t)c; };
-    auto Cb = [&](int k) { return gpool + fptr[b * LMAX_CAP + k]; };
-    auto Qb = [&](int k) { return gpool + fptr[b * LMAX_CAP + k] + 9 * (int64_t)c; };
+    auto Cb = [&](int k) { return gpool + goff[b] + 9 * (int64_t)k * (c + q); };
+    auto Qb = [&](int k) { return gpool + goff[b] + 9 * (int64_t)k * (c + q) + 9 * (int64_t)c; };
     // t_k = sum_j q_k(j) F_j, tb_k = sum_i c_k(i)^T w_i
     for (int k = 0; k < l; ++k) {
       double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -374,12 +381,12 @@ __global__ __launch_bounds__(TB) void k_aca_adjoint(
 
 // Back-propagation of the sampled far pairs: workgroup per (block, term k).
 template <class T>
-__global__ __launch_bounds__(TB) void k_far_vjp(const int2* __restrict__ G, int64_t nG,
-                                                const int4* __restrict__ nodes,
+__global__ __launch_bounds__(TB) void k_far_vjp(const int2* __restrict__ G, int64_t b0,
+                                                int64_t b1, const int4* __restrict__ nodes,
                                                 const int32_t* __restrict__ rank,
                                                 const int32_t* __restrict__ flag,
                                                 const int32_t* __restrict__ piv,
-                                                const int64_t* __restrict__ fptr,
+                                                const int64_t* __restrict__ goff,
                                                 const T* __restrict__ gpool,
                                                 const double* __restrict__ xs,
                                                 const T* __restrict__ wgt, int mode,
@@ -389,14 +396,14 @@ __global__ __launch_bounds__(TB) void k_far_vjp(const int2* __restrict__ G, int6
   __shared__ double dth[MLP_NP];
   stage_params(wl, dth, wgt);
   __syncthreads();
-  for (int64_t b = blockIdx.x; b < nG; b += gridDim.x) {
+  for (int64_t b = b0 + blockIdx.x; b < b1; b += gridDim.x) {
     if (flag[b] || rank[b] == 0) continue;
     const int2 g = G[b];
     const int4 nt = nodes[g.x], ns = nodes[g.y];
     const int c = nt.y - nt.x, q = ns.y - ns.x, l = rank[b];
     for (int k = 0; k < l; ++k) {
       const int ik = piv[b * 2 * LMAX_CAP + k], jk = piv[b * 2 * LMAX_CAP + LMAX_CAP + k];
-      const T* gc = gpool + fptr[b * LMAX_CAP + k];
+      const T* gc = gpool + goff[b] + 9 * (int64_t)k * (c + q);
       const T* gr = gc + 9 * (int64_t)c;
       for (int t = threadIdx.x; t < c + q; t += TB) {
         const bool colp = t < c;
@@ -528,14 +535,35 @@ void backward_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kernel k, co
   HIP_OK(hipMemsetAsync(farT.p, 0, 3 * n * sizeof(double), st));
   const bool mlp = k->kind == KIND_MLP && (dX || dparams);
   const int64_t nG = p->nG;
+  // cotangent pool: the blocks in chunks of consecutive blocks whose
+  // cotangents (rank 9 (c + q) values each) fit GPOOL_CHUNK elements (a block
+  // larger than that is a chunk of its own); each chunk's adjoint is
+  // followed by the back-propagation of its sampled pairs
+  std::vector<int64_t> bounds(1, 0);
+  int64_t chunk_max = 1;
+  DevBuf goff;
   if (nG > 0 && (dF || mlp)) {
-    gpool.alloc(st, std::max<int64_t>(lr->used_elems, 1) * sizeof(T));
-    int grid = (int)std::min<int64_t>(nG, 4096);
-    hipLaunchKernelGGL((k_aca_adjoint<T>), dim3(grid), dim3(TB), 0, st, p->G.as<int2>(), nG,
-                       t->nodes.as<int4>(), lr->rank.as<int32_t>(), lr->flag.as<int32_t>(),
-                       lr->piv.as<int32_t>(), lr->fptr.as<int64_t>(), lr->pool.as<T>(),
-                       gpool.as<T>(), Fs.as<T>(), ws.as<T>(), farT.as<double>());
-    HIP_OK(hipGetLastError());
+    std::vector<int32_t> cs, qs, rk(nG), fl(nG);
+    block_sizes(ctx, t, p, cs, qs);
+    read_bytes(ctx, rk.data(), lr->rank.p, nG * sizeof(int32_t));
+    read_bytes(ctx, fl.data(), lr->flag.p, nG * sizeof(int32_t));
+    std::vector<int64_t> off(nG);
+    int64_t cur = 0;
+    for (int64_t b = 0; b < nG; ++b) {
+      const int64_t need = fl[b] ? 0 : 9 * (int64_t)rk[b] * ((int64_t)cs[b] + qs[b]);
+      if (cur > 0 && cur + need > GPOOL_CHUNK) {
+        bounds.push_back(b);
+        chunk_max = std::max(chunk_max, cur);
+        cur = 0;
+      }
+      off[b] = cur;
+      cur += need;
+    }
+    chunk_max = std::max(chunk_max, cur);
+    bounds.push_back(nG);
+    goff.alloc(st, nG * sizeof(int64_t));
+    HIP_OK(hipMemcpyAsync(goff.p, off.data(), nG * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    gpool.alloc(st, chunk_max * sizeof(T));
   }
   const int gfb = (int)std::min<int64_t>(std::max<int64_t>(nG, 1), 256);
   if (mlp) {
@@ -548,6 +576,24 @@ void backward_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kernel k, co
   if (mlp) {
     part.alloc(st, (int64_t)nparts * MLP_NP * sizeof(double));
     HIP_OK(hipMemsetAsync(part.p, 0, (int64_t)nparts * MLP_NP * sizeof(double), st));
+  }
+  const T* wgt = (const T*)(sizeof(T) == 8 ? k->p64.p : k->p32.p);
+  for (size_t c = 0; c + 1 < bounds.size(); ++c) {
+    const int64_t b0 = bounds[c], b1 = bounds[c + 1];
+    if (b1 <= b0) continue;
+    const unsigned grid = (unsigned)std::min<int64_t>(b1 - b0, 4096);
+    hipLaunchKernelGGL((k_aca_adjoint<T>), dim3(grid), dim3(TB), 0, st, p->G.as<int2>(), b0, b1,
+                       t->nodes.as<int4>(), lr->rank.as<int32_t>(), lr->flag.as<int32_t>(),
+                       lr->piv.as<int32_t>(), lr->fptr.as<int64_t>(), goff.as<int64_t>(),
+                       lr->pool.as<T>(), gpool.as<T>(), Fs.as<T>(), ws.as<T>(),
+                       farT.as<double>());
+    if (mlp)
+      hipLaunchKernelGGL((k_far_vjp<T>), dim3(gfar), dim3(TB), 0, st, p->G.as<int2>(), b0, b1,
+                         t->nodes.as<int4>(), lr->rank.as<int32_t>(), lr->flag.as<int32_t>(),
+                         lr->piv.as<int32_t>(), goff.as<int64_t>(), gpool.as<T>(),
+                         t->xs.as<double>(), wgt, k->input_mode, dXs.as<double>(),
+                         part.as<double>() + (int64_t)gnear * MLP_NP);
+    HIP_OK(hipGetLastError());
   }
   if (lr->n_fallback > 0 && (dF || mlp)) {
     const KParams kp = make_kparams(k, sizeof(T) == 8);
@@ -572,17 +618,10 @@ void backward_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kernel k, co
                        (T*)dF);
   }
   if (mlp) {
-    const T* wgt = (const T*)(sizeof(T) == 8 ? k->p64.p : k->p32.p);
     hipLaunchKernelGGL((k_near_vjp<T>), dim3(gnear), dim3(TB), 0, st, t->nodes.as<int4>(),
                        t->leaves.as<int32_t>(), p->near_ptr.as<int32_t>(), p->H.as<int2>(),
                        t->xs.as<double>(), Fs.as<T>(), ws.as<T>(), wgt, k->input_mode,
                        dXs.as<double>(), part.as<double>());
-    if (nG > 0)
-      hipLaunchKernelGGL((k_far_vjp<T>), dim3(gfar), dim3(TB), 0, st, p->G.as<int2>(), nG,
-                         t->nodes.as<int4>(), lr->rank.as<int32_t>(), lr->flag.as<int32_t>(),
-                         lr->piv.as<int32_t>(), lr->fptr.as<int64_t>(), gpool.as<T>(),
-                         t->xs.as<double>(), wgt, k->input_mode, dXs.as<double>(),
-                         part.as<double>() + (int64_t)gnear * MLP_NP);
     HIP_OK(hipGetLastError());
     if (dX)
       hipLaunchKernelGGL(k_scatter_dX, dim3(nblk(n)), dim3(TB), 0, st, dXs.as<double>(),

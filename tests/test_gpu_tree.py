@@ -35,13 +35,12 @@ def test_tree_and_partition_bit_exact(geom, n, phi, c_leaf, seed):
     assert np.array_equal(ex["keys"], ref.keys)
     assert np.array_equal(ex["nodes"], ref.nodes)
     assert np.array_equal(ex["bbox"], ref.bbox)
-    if n <= 20000:
-        for eta in (1.0, 0.5):
-            say("partition", n, eta)
-            G, H = OP.build_partition(ref, eta)
-            p = hh.partition(ctx(), t, eta)
-            g, h = p.export()
-            assert np.array_equal(g, G) and np.array_equal(h, H)
+    for eta in (1.0, 0.5):
+        say("partition", n, eta)
+        G, H = OP.build_partition(ref, eta)
+        p = hh.partition(ctx(), t, eta)
+        g, h = p.export()
+        assert np.array_equal(g, G) and np.array_equal(h, H)
 
 
 def test_small_and_degenerate_sizes():
