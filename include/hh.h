@@ -221,6 +221,25 @@ hh_status hh_aca_build_pivots(hh_ctx ctx, hh_tree tree, hh_part part, hh_kernel 
 hh_status hh_matvec(hh_ctx ctx, hh_tree tree, hh_part part, hh_lowrank lr, hh_kernel kern,
                     hh_precision prec, const void* F, void* U);
 
+/* Bytes of the static device scratch of hh_matvec_noalloc (one copy per
+ * device, held until the process ends). */
+#define HH_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * product of hh_matvec (same kernels, same result bit for bit) with its
+ * workspaces -- the sorted forces and the near-field rows, 3 n values each --
+ * in a file-scope device array of HH_NOALLOC_SCRATCH_BYTES instead of device
+ * memory kept in lr; it calls no allocating routine and records no phase
+ * events. Stored factors only (a streamed-mode lr -> HH_ERR_INVALID_ARG). A
+ * product that needs more scratch than HH_NOALLOC_SCRATCH_BYTES (about 1.4M
+ * particles in HH_FP64, 1.8M in HH_BF16, 2.8M in HH_FP32) -> HH_ERR_CAPACITY,
+ * checked before anything else. Every call on a device shares that device's
+ * scratch: calls that overlap in time on one device (any streams, any
+ * contexts) race and must be ordered by the caller. Does not sync. */
+hh_status hh_matvec_noalloc(hh_ctx ctx, hh_tree tree, hh_part part, hh_lowrank lr,
+                            hh_kernel kern, hh_precision prec, const void* F, void* U);
+
 /* Gradients of L = sum_i dU_i . U_i for the product hh_matvec computes, with
  * the tree, the partition and the ACA pivots frozen.
  *   dF (device, same type as F, nullable): the transposed product M_H^T dU.

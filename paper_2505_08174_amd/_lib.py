@@ -59,6 +59,7 @@ SIGNATURES = {
                                 C.POINTER(_vp), C.POINTER(_vp)]),
     "hh_batch_free": (None, [_vp]),
     "hh_matvec": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int, _vp, _vp]),
+    "hh_matvec_noalloc": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int, _vp, _vp]),
     "hh_matvec_backward": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int, _vp, _vp, _vp, _vp, _vp]),
     "hh_tree_free": (None, [_vp]),
     "hh_part_free": (None, [_vp]),

@@ -287,6 +287,18 @@ def matvec(ctx: Context, tree: Tree, part: Partition, lr: LowRank, kern: Kernel,
     return U
 
 
+def matvec_noalloc(ctx: Context, tree: Tree, part: Partition, lr: LowRank, kern: Kernel,
+                   F: torch.Tensor, U: torch.Tensor, prec="fp64") -> torch.Tensor:
+    """hh_matvec_noalloc: the stored-mode product with its workspaces in the
+    library's static device scratch (U must be given: nothing is allocated)."""
+    p = _prec(prec)
+    assert F.is_cuda and F.dtype == F_DTYPE[p] and F.is_contiguous()
+    assert U.dtype == U_DTYPE[p] and U.is_contiguous() and U.shape == F.shape
+    ctx.check(L.load().hh_matvec_noalloc(ctx.h, tree.h, part.h, lr.h, kern.h, p, _ptr(F),
+                                         _ptr(U)))
+    return U
+
+
 def matvec_backward(ctx: Context, tree: Tree, part: Partition, lr: LowRank, kern: Kernel,
                     F: torch.Tensor, dU: torch.Tensor, prec="fp64", want=("F", "X", "theta")):
     """(dF, dX, dtheta) of L = sum dU . U with the structure frozen (None where

@@ -235,6 +235,21 @@ void matvec_ws_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kernel k, c
   matvec_t<T, TI, TO, TU>(ctx, t, p, lr, k, F, U, lr->ws_f.p, lr->ws_near.p, true);
 }
 
+// The allocation-free product: the same launches with the workspaces in the
+// device's static scratch (base, HH_NOALLOC_SCRATCH_BYTES).
+template <class T, class TI, class TO, class TU>
+void matvec_noalloc_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kernel k,
+                      const void* F, void* U, char* base) {
+  const int64_t n = t->n;
+  const int64_t bf = (3 * n * (int64_t)sizeof(T) + 255) / 256 * 256;
+  const int64_t bu = 3 * n * (int64_t)sizeof(TU);
+  HH_REQUIRE(bf + bu <= (int64_t)HH_NOALLOC_SCRATCH_BYTES, HH_ERR_CAPACITY,
+             "hh_matvec_noalloc: " + std::to_string(n) + " particles need " +
+                 std::to_string(bf + bu) + " bytes of scratch, more than the " +
+                 std::to_string((int64_t)HH_NOALLOC_SCRATCH_BYTES) + " available");
+  matvec_t<T, TI, TO, TU>(ctx, t, p, lr, k, F, U, base, base + bf, false);
+}
+
 template <class T, class TI, class TO, class TU>
 void matvec_streamed_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kernel k,
                        const void* F, void* U) {
@@ -371,6 +386,39 @@ hh_status hh_matvec(hh_ctx ctx, hh_tree tree, hh_part part, hh_lowrank lr, hh_ke
   } else {
     matvec_ws_t<float, float, double, float>(ctx, tree, part, lr, kern, F, U);
   }
+  HH_API_END(ctx)
+}
+
+hh_status hh_matvec_noalloc(hh_ctx ctx, hh_tree tree, hh_part part, hh_lowrank lr,
+                            hh_kernel kern, hh_precision prec, const void* F, void* U) {
+  HH_API_BEGIN(ctx)
+  HH_REQUIRE(tree && part && lr && kern && F && U, HH_ERR_INVALID_ARG, "NULL argument");
+  HH_REQUIRE(part->tree == tree && lr->part == part, HH_ERR_INVALID_ARG,
+             "handles do not belong together");
+  HH_REQUIRE(lr->prec == prec, HH_ERR_INVALID_ARG, "precision differs from the ACA build");
+  HH_REQUIRE(lr->kern == kern, HH_ERR_INVALID_ARG, "kernel differs from the ACA build");
+  HH_REQUIRE(ctx->noalloc_scratch, HH_ERR_HIP, "no scratch address on this device");
+  char* base = (char*)ctx->noalloc_scratch;
+  const bool mfma = is_bf16(prec) && kern->kind == KIND_MLP;
+  // the size limit first: it depends only on n and the precision
+  const int64_t n = tree->n;
+  const int64_t need = (3 * n * (prec == HH_FP64 ? 8 : 4) + 255) / 256 * 256 +
+                       3 * n * ((prec == HH_FP64 || mfma) ? 8 : 4);
+  HH_REQUIRE(need <= (int64_t)HH_NOALLOC_SCRATCH_BYTES, HH_ERR_CAPACITY,
+             "hh_matvec_noalloc: " + std::to_string(n) + " particles need " +
+                 std::to_string(need) + " bytes of scratch, more than the " +
+                 std::to_string((int64_t)HH_NOALLOC_SCRATCH_BYTES) + " available");
+  HH_REQUIRE(!lr->streamed, HH_ERR_INVALID_ARG,
+             "hh_matvec_noalloc needs stored factors (streamed mode runs the ACA in the product)");
+  HH_REQUIRE(tree->n_units > 0, HH_ERR_INVALID_ARG, "tree has no near-field work units");
+  if (prec == HH_FP64)
+    matvec_noalloc_t<double, double, double, double>(ctx, tree, part, lr, kern, F, U, base);
+  else if (prec == HH_FP32)
+    matvec_noalloc_t<float, float, float, float>(ctx, tree, part, lr, kern, F, U, base);
+  else if (mfma)
+    matvec_noalloc_t<float, float, double, double>(ctx, tree, part, lr, kern, F, U, base);
+  else
+    matvec_noalloc_t<float, float, double, float>(ctx, tree, part, lr, kern, F, U, base);
   HH_API_END(ctx)
 }
 

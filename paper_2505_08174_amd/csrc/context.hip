@@ -2,6 +2,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "api_guard.h"
@@ -92,7 +93,30 @@ KParams make_kparams(hh_kernel k, bool fp64) {
   return kp;
 }
 
+// Device memory of hh_matvec_noalloc: the sorted forces and the near-field
+// rows of one product. In host code this name is only a stand-in for the
+// symbol; each device's address comes from hipGetSymbolAddress, taken once
+// per device when the first context is created on it.
+static __device__ __align__(256) unsigned char scratch[HH_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {nullptr};
+
+// This device's copy of the scratch array (the device must be current).
+void* scratch_address(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  HH_REQUIRE(device >= 0 && device < MAX_DEVICES, HH_ERR_INVALID_ARG, "device id out of range");
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    HH_REQUIRE(p, HH_ERR_HIP, "no device address for the no-allocation scratch");
+    g_scratch_ptr[device] = p;
+  }
+  return g_scratch_ptr[device];
+}
+
 __global__ void k_zero_words(int64_t* __restrict__ p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
     p[i] = 0;
@@ -220,6 +244,7 @@ hh_status hh_ctx_create(int device, void* stream, hh_ctx* out) {
     ctx->device = device;
     ctx->stream = (hipStream_t)stream;
     HIP_OK(hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, device));
+    ctx->noalloc_scratch = scratch_address(device);
     HIP_OK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
     HIP_OK(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
     HIP_OK(hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming));

@@ -75,6 +75,9 @@ struct hh_ctx_s {
   int team_cls = 12;           // blocks with c + q >= 2^team_cls go to whole workgroups
   double phase_ms[HH_NPHASE] = {0};
   int64_t phase_cnt[HH_NPHASE] = {0};
+  // this device's copy of the static scratch of hh_matvec_noalloc
+  // (HH_NOALLOC_SCRATCH_BYTES), located when the context was created
+  void* noalloc_scratch = nullptr;
 };
 
 // Records HIP events around a phase when profiling is on (RAII).
