@@ -42,7 +42,8 @@ TANH_PER_CLK_CU = 16
 CU, CLK = 256, 2.4e9
 # sources whose change invalidates the stored HBM traffic of a kernel
 KERNEL_SOURCES = {"k_aca": ["aca.hip", "mlp_mfma.h", "devmath.h", "internal.h"],
-                  "k_near": ["near_mfma.hip", "near.hip", "mlp_mfma.h", "devmath.h", "internal.h"]}
+                  "k_near": ["near_mfma.hip", "near.hip", "mlp_mfma.h", "devmath.h", "internal.h"],
+                  "far": ["apply.hip", "internal.h"]}
 
 
 def log(*a):
@@ -64,6 +65,9 @@ def parse():
     ap.add_argument("--autotune", action="store_true",
                     help="pick leaf sizes (per size class of systems) and the workgroup "
                          "threshold by timing whole steps first (not timed)")
+    ap.add_argument("--budget-gb", type=float, default=None,
+                    help="device memory the ACA factors may use (hh_ctx_set_budget); factors "
+                         "that fit half of it are stored, else the ACA is streamed")
     ap.add_argument("--backward", action="store_true",
                     help="time the step plus hh_matvec_backward (dF, dX, dtheta of "
                          "L = w . U), FP32 or FP64 forms")
@@ -90,6 +94,42 @@ def stored_traffic(kernel, workload):
     if rec.get("source_sha256") != sources_sha(kernel):
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def _profile_json(name):
+    try:
+        with open(os.path.join(ROOT, "profiles", name)) as fh:
+            return json.loads(fh.read().split("\n---\n")[0])
+    except (OSError, ValueError):
+        return None
+
+
+def stored_counters(workload):
+    """MFMA utilisation of the kernel-MLP kernels and HBM rates of the far-field
+    apply from the committed profiler summaries, each while the sources it was
+    taken on are unchanged (else omitted)."""
+    out = {}
+    m = _profile_json("mlp_mfma_%s_counters.txt" % workload)
+    if m:
+        for k, rec in m["kernels"].items():
+            key = "k_near" if k.startswith("k_near") else "k_aca"
+            if m.get("source_sha256_" + key) != sources_sha(key):
+                continue
+            out[k] = {"mfma_busy_frac": round(rec["mfma_busy_frac"], 4),
+                      "mfma_bf16_TFs_issued": round(rec["mfma_bf16_TFs_issued"], 1),
+                      "mfma_issued_frac_of_peak": round(rec["mfma_issued_frac_of_peak"], 4),
+                      "source": "profiles/mlp_mfma_%s_counters.txt" % workload}
+    f = _profile_json("far_apply_traffic.txt")
+    if f and f.get("source_sha256") == sources_sha("far"):
+        st = f["stored"]
+        out["far_apply"] = {
+            "stored_hbm_GBs": round(st["measured_GBs"], 1),
+            "stored_frac_of_hbm_peak": round(st["measured_GBs"] / PEAK["hbm_GBs"], 4),
+            "stored_workload": st["workload"],
+            "streamed_k_far_gather_hbm_GBs": round(f["streamed"]["hbm_GBs"], 1),
+            "streamed_workload": "precision_1m",
+            "source": "profiles/far_apply_traffic.txt"}
+    return out
 
 
 def golden_rows(workload, X, F):
@@ -216,10 +256,13 @@ def main():
         tuned["seconds"] = round(time.perf_counter() - t0, 1)
         log("autotuned:", tuned)
 
+    if a.budget_gb is not None:
+        ctx.set_budget(int(a.budget_gb * (1 << 30)))
     if a.backward:
         # cotangent w ~ N(0, I3); the backward needs stored factors
         wd = torch.tensor(wl.normal_forces(n, seed=5), dtype=fdt, device="cuda:0")
-        ctx.set_budget(200 << 30)
+        if a.budget_gb is None:
+            ctx.set_budget(280 << 30)
 
     def step():
         if offsets is None:
@@ -300,6 +343,7 @@ def main():
                    "eta": cfg["eta"], "eps": cfg["eps"],
                    "l_max": a.l_max, "geometry": cfg["geom"], "phi": cfg["phi"],
                    "systems": 1 if offsets is None else len(offsets) - 1,
+                   "factors": "stored" if li["bytes"] > 0 else "streamed",
                    "backward": bool(a.backward)},
         "phases_ms": {k: round(v, 3) for k, v in per_step.items()},
         "work": {"nodes": nn, "leaves": nl, "blocks_G": nG, "blocks_H": nH,
@@ -307,6 +351,7 @@ def main():
                  "rank_sum": li["rank_sum"], "fallbacks": li["n_fallback"],
                  "factor_bytes": li["bytes"]},
         "roofline": roof,
+        "counters": stored_counters(a.workload),
     }
     gold = golden_rows(a.workload, X, F) if a.n is None and offsets is None else None
     if gold is not None:

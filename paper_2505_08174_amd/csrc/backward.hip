@@ -27,13 +27,74 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + TB - 1) / TB); }
 // cotangent-pool elements per chunk of blocks (1 GiB in FP32)
 constexpr int64_t GPOOL_CHUNK = 256ll << 20;
 
-// dtheta accumulates in FP64 in LDS in every form (one workgroup adds the
-// contributions of up to ~1e6 pairs per parameter).
-__device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); }
+// dtheta: every wave sums its 64 lanes' contributions to a parameter with DPP
+// (all lanes active, a fixed order), and one lane per wave adds the total to
+// the workgroup's FP64 accumulator in LDS, up to 64 parameters per atomic
+// instruction (one per lane, distinct addresses).
+
+// v + (v of the source lane given by a DPP control); 0 from lanes outside the
+// row or in rows masked off
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float v) {
+  const int x = __float_as_int(v);
+  const int s = ROW_MASK == 0xf ? __builtin_amdgcn_update_dpp(x, x, CTRL, 0xf, 0xf, true)
+                                : __builtin_amdgcn_update_dpp(0, x, CTRL, ROW_MASK, 0xf, false);
+  return v + __int_as_float(s);
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  int slo, shi;
+  if (ROW_MASK == 0xf) {
+    slo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, true);
+    shi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, true);
+  } else {
+    slo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xf, false);
+    shi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xf, false);
+  }
+  return v + __hiloint2double(shi, slo);
+}
+
+// Sum over the 64 lanes (every lane active), returned in every lane: scans
+// by row shifts 1, 2, 4, 8 in each 16-lane row, then the lane-15 and lane-31
+// row broadcasts carry the row sums into lane 63.
+template <class T>
+__device__ __forceinline__ T wave_total(T v) {
+  v = dpp_add<0x111, 0xf>(v);
+  v = dpp_add<0x112, 0xf>(v);
+  v = dpp_add<0x114, 0xf>(v);
+  v = dpp_add<0x118, 0xf>(v);
+  v = dpp_add<0x142, 0xa>(v);
+  v = dpp_add<0x143, 0xc>(v);
+  if constexpr (sizeof(T) == 4) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+  } else {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+  }
+}
+
+// Wave totals of up to 64 parameters, total k kept in lane k, then added to
+// dth[base + stride * lane] (one LDS atomic instruction).
+template <class T>
+struct RowSum {
+  T r = 0;
+  __device__ __forceinline__ void put(int k, T v) {
+    const T t = wave_total(v);
+    r = (int)(threadIdx.x & 63) == k ? t : r;
+  }
+  __device__ __forceinline__ void flush(double* base, int count, int stride = 1) {
+    const int lane = threadIdx.x & 63;
+    if (lane < count) atomicAdd(base + stride * lane, (double)r);
+    r = 0;
+  }
+};
 
 // Cotangent of one kernel entry K(r) (3x3, symmetric) for the MLP kernel:
-// adds d/dtheta of sum_ab gb_ab K_ab(r) into dth (LDS, packed layout) and
-// returns d/dr.
+// adds d/dtheta of sum_ab gb_ab K_ab(r) over the wave's 64 lanes into dth
+// (LDS, packed layout) and returns this lane's d/dr. Every lane of the wave
+// must call it (a lane with nothing to add passes gb = 0 and any r != 0).
 template <class T>
 __device__ void mlp_vjp(const T* __restrict__ P, int mode, T rx, T ry, T rz,
                         const T gb[9], double* __restrict__ dth, T dr[3]) {
@@ -68,50 +129,65 @@ __device__ void mlp_vjp(const T* __restrict__ P, int mode, T rx, T ry, T rz,
     for (int b = 0; b < 3; ++b) g[3 * a + b] = T(0.5) * (gb[3 * a + b] + gb[3 * b + a]);
   const T s = id * T(1.0 / (8.0 * HH_PI));
   T og = 0, d4[9];
+  RowSum<T> rb;
   for (int m = 0; m < 9; ++m) {
     og += o[m] * g[m];
     d4[m] = s * g[m];
-    lds_add(&dth[OFF_B4 + m], d4[m]);
+    rb.put(m, d4[m]);
   }
+  rb.flush(&dth[OFF_B4], 9);
   for (int k = 0; k < MLP_H; ++k) {
     T acc = 0;
-    for (int m = 0; m < 9; ++m) {
-      lds_add(&dth[OFF_W4 + MLP_H * m + k], d4[m] * h3[k]);
-      acc += P[OFF_W4 + MLP_H * m + k] * d4[m];
-    }
+    for (int m = 0; m < 9; ++m) acc += P[OFF_W4 + MLP_H * m + k] * d4[m];
     dl[k] = acc * (T(1) - h3[k] * h3[k]);   // delta_3
+  }
+  for (int m = 0; m < 9; ++m) {
+    RowSum<T> rw;
+    for (int k = 0; k < MLP_H; ++k) rw.put(k, d4[m] * h3[k]);
+    rw.flush(&dth[OFF_W4 + MLP_H * m], MLP_H);
   }
   // layer 3: delta_3 -> dW3, db3, delta_2 (into h3, no longer needed)
   for (int k = 0; k < MLP_H; ++k) h3[k] = 0;
   for (int a = 0; a < MLP_H; ++a) {
     const T da = dl[a];
-    lds_add(&dth[OFF_B3 + a], da);
+    rb.put(a, da);
+    RowSum<T> rw;
     for (int k = 0; k < MLP_H; ++k) {
-      lds_add(&dth[OFF_W3 + MLP_H * a + k], da * h2[k]);
+      rw.put(k, da * h2[k]);
       h3[k] += P[OFF_W3 + MLP_H * a + k] * da;
     }
+    rw.flush(&dth[OFF_W3 + MLP_H * a], MLP_H);
   }
+  rb.flush(&dth[OFF_B3], MLP_H);
   for (int k = 0; k < MLP_H; ++k) dl[k] = h3[k] * (T(1) - h2[k] * h2[k]);   // delta_2
   for (int k = 0; k < MLP_H; ++k) h3[k] = 0;
   for (int a = 0; a < MLP_H; ++a) {
     const T da = dl[a];
-    lds_add(&dth[OFF_B2 + a], da);
+    rb.put(a, da);
+    RowSum<T> rw;
     for (int k = 0; k < MLP_H; ++k) {
-      lds_add(&dth[OFF_W2 + MLP_H * a + k], da * h1[k]);
+      rw.put(k, da * h1[k]);
       h3[k] += P[OFF_W2 + MLP_H * a + k] * da;
     }
+    rw.flush(&dth[OFF_W2 + MLP_H * a], MLP_H);
   }
+  rb.flush(&dth[OFF_B2], MLP_H);
   T gv0 = 0, gv1 = 0, gv2 = 0;
+  RowSum<T> r0, r1, r2;
   for (int k = 0; k < MLP_H; ++k) {
     const T d1 = h3[k] * (T(1) - h1[k] * h1[k]);   // delta_1
-    lds_add(&dth[OFF_B1 + k], d1);
-    lds_add(&dth[OFF_W1 + 3 * k], d1 * v0);
-    lds_add(&dth[OFF_W1 + 3 * k + 1], d1 * v1);
-    lds_add(&dth[OFF_W1 + 3 * k + 2], d1 * v2);
+    rb.put(k, d1);
+    r0.put(k, d1 * v0);
+    r1.put(k, d1 * v1);
+    r2.put(k, d1 * v2);
     gv0 += P[OFF_W1 + 3 * k] * d1;
     gv1 += P[OFF_W1 + 3 * k + 1] * d1;
     gv2 += P[OFF_W1 + 3 * k + 2] * d1;
   }
+  rb.flush(&dth[OFF_B1], MLP_H);
+  r0.flush(&dth[OFF_W1], MLP_H, 3);
+  r1.flush(&dth[OFF_W1 + 1], MLP_H, 3);
+  r2.flush(&dth[OFF_W1 + 2], MLP_H, 3);
   if (dir) {
     const T vg = v0 * gv0 + v1 * gv1 + v2 * gv2;
     gv0 = (gv0 - v0 * vg) * id;
@@ -160,27 +236,36 @@ __global__ __launch_bounds__(TB) void k_near_vjp(const int4* __restrict__ nodes,
   __syncthreads();
   const int leaf = blockIdx.x;
   const int4 nt = nodes[leaves[leaf]];
+  const int w64 = threadIdx.x & ~63;   // first thread of this wave
   for (int ib = nt.x; ib < nt.y; ib += TB) {
+    if (ib + w64 >= nt.y) continue;   // the whole wave past the leaf (uniform)
+    // every lane of the wave runs every pair (mlp_vjp reduces across the
+    // wave); a lane past the leaf or on its own particle adds nothing
     const int i = ib + threadIdx.x;
-    if (i < nt.y) {
-      const double x0 = xs[3 * (int64_t)i], x1 = xs[3 * (int64_t)i + 1], x2 = xs[3 * (int64_t)i + 2];
-      const T w0 = ws[3 * (int64_t)i], w1 = ws[3 * (int64_t)i + 1], w2 = ws[3 * (int64_t)i + 2];
-      double a0 = 0, a1 = 0, a2 = 0;
-      for (int p = near_ptr[leaf]; p < near_ptr[leaf + 1]; ++p) {
-        const int4 ns = nodes[H[p].y];
-        for (int j = ns.x; j < ns.y; ++j) {
-          if (j == i) continue;
-          const T f0 = Fs[3 * (int64_t)j], f1 = Fs[3 * (int64_t)j + 1], f2 = Fs[3 * (int64_t)j + 2];
-          T gb[9] = {w0 * f0, w0 * f1, w0 * f2, w1 * f0, w1 * f1, w1 * f2, w2 * f0, w2 * f1, w2 * f2};
-          T dr[3];
-          mlp_vjp<T>(wl, mode, (T)(x0 - xs[3 * (int64_t)j]), (T)(x1 - xs[3 * (int64_t)j + 1]),
-                     (T)(x2 - xs[3 * (int64_t)j + 2]), gb, dth, dr);
+    const bool vi = i < nt.y;
+    const int ii = vi ? i : nt.x;
+    const double x0 = xs[3 * (int64_t)ii], x1 = xs[3 * (int64_t)ii + 1], x2 = xs[3 * (int64_t)ii + 2];
+    const T w0 = ws[3 * (int64_t)ii], w1 = ws[3 * (int64_t)ii + 1], w2 = ws[3 * (int64_t)ii + 2];
+    double a0 = 0, a1 = 0, a2 = 0;
+    for (int p = near_ptr[leaf]; p < near_ptr[leaf + 1]; ++p) {
+      const int4 ns = nodes[H[p].y];
+      for (int j = ns.x; j < ns.y; ++j) {
+        const bool ok = vi && j != i;
+        const T f0 = Fs[3 * (int64_t)j], f1 = Fs[3 * (int64_t)j + 1], f2 = Fs[3 * (int64_t)j + 2];
+        const T u0 = ok ? w0 : T(0), u1 = ok ? w1 : T(0), u2 = ok ? w2 : T(0);
+        T gb[9] = {u0 * f0, u0 * f1, u0 * f2, u1 * f0, u1 * f1, u1 * f2, u2 * f0, u2 * f1, u2 * f2};
+        T dr[3];
+        const T rx = ok ? (T)(x0 - xs[3 * (int64_t)j]) : T(1);
+        const T ry = ok ? (T)(x1 - xs[3 * (int64_t)j + 1]) : T(0);
+        const T rz = ok ? (T)(x2 - xs[3 * (int64_t)j + 2]) : T(0);
+        mlp_vjp<T>(wl, mode, rx, ry, rz, gb, dth, dr);
+        if (ok) {
           a0 += dr[0]; a1 += dr[1]; a2 += dr[2];
           atomic_add3(dXs + 3 * (int64_t)j, -(double)dr[0], -(double)dr[1], -(double)dr[2]);
         }
       }
-      atomic_add3(dXs + 3 * (int64_t)i, a0, a1, a2);
     }
+    if (vi) atomic_add3(dXs + 3 * (int64_t)i, a0, a1, a2);
   }
   __syncthreads();
   flush_params(dth, part);
@@ -405,19 +490,26 @@ __global__ __launch_bounds__(TB) void k_far_vjp(const int2* __restrict__ G, int6
       const int ik = piv[b * 2 * LMAX_CAP + k], jk = piv[b * 2 * LMAX_CAP + LMAX_CAP + k];
       const T* gc = gpool + goff[b] + 9 * (int64_t)k * (c + q);
       const T* gr = gc + 9 * (int64_t)c;
-      for (int t = threadIdx.x; t < c + q; t += TB) {
-        const bool colp = t < c;
-        const int i = colp ? nt.x + t : nt.x + ik;
-        const int j = colp ? ns.x + jk : ns.x + (t - c);
-        const T* gsrc = colp ? gc + 9 * (int64_t)t : gr + 9 * (int64_t)(t - c);
+      const int w64 = threadIdx.x & ~63;
+      for (int t0 = 0; t0 < c + q; t0 += TB) {
+        if (t0 + w64 >= c + q) continue;   // the whole wave past the samples (uniform)
+        const int t = t0 + threadIdx.x;
+        const bool ok = t < c + q;         // lanes past the samples add nothing
+        const int tt = ok ? t : 0;
+        const bool colp = tt < c;
+        const int i = colp ? nt.x + tt : nt.x + ik;
+        const int j = colp ? ns.x + jk : ns.x + (tt - c);
+        const T* gsrc = colp ? gc + 9 * (int64_t)tt : gr + 9 * (int64_t)(tt - c);
         T gb[9];
-        for (int e = 0; e < 9; ++e) gb[e] = gsrc[e];
+        for (int e = 0; e < 9; ++e) gb[e] = ok ? gsrc[e] : T(0);
         T dr[3];
         mlp_vjp<T>(wl, mode, (T)(xs[3 * (int64_t)i] - xs[3 * (int64_t)j]),
                    (T)(xs[3 * (int64_t)i + 1] - xs[3 * (int64_t)j + 1]),
                    (T)(xs[3 * (int64_t)i + 2] - xs[3 * (int64_t)j + 2]), gb, dth, dr);
-        atomic_add3(dXs + 3 * (int64_t)i, dr[0], dr[1], dr[2]);
-        atomic_add3(dXs + 3 * (int64_t)j, -(double)dr[0], -(double)dr[1], -(double)dr[2]);
+        if (ok) {
+          atomic_add3(dXs + 3 * (int64_t)i, dr[0], dr[1], dr[2]);
+          atomic_add3(dXs + 3 * (int64_t)j, -(double)dr[0], -(double)dr[1], -(double)dr[2]);
+        }
       }
     }
   }
@@ -444,28 +536,37 @@ __global__ __launch_bounds__(TB) void k_fallback_bwd(const int2* __restrict__ G,
   for (int64_t b = blockIdx.x; b < nG; b += gridDim.x) {
     if (!flag[b]) continue;
     const int4 nt = nodes[G[b].x], ns = nodes[G[b].y];
-    for (int i = nt.x + threadIdx.x; i < nt.y; i += TB) {
-      const double x0 = xs[3 * (int64_t)i], x1 = xs[3 * (int64_t)i + 1], x2 = xs[3 * (int64_t)i + 2];
-      const T w0 = ws[3 * (int64_t)i], w1 = ws[3 * (int64_t)i + 1], w2 = ws[3 * (int64_t)i + 2];
+    const int w64 = threadIdx.x & ~63;
+    for (int ib = nt.x; ib < nt.y; ib += TB) {
+      if (ib + w64 >= nt.y) continue;   // the whole wave past the block (uniform)
+      const int i = ib + threadIdx.x;
+      const bool vi = i < nt.y;          // lanes past the block add nothing
+      const int ii = vi ? i : nt.x;
+      const double x0 = xs[3 * (int64_t)ii], x1 = xs[3 * (int64_t)ii + 1], x2 = xs[3 * (int64_t)ii + 2];
+      const T w0 = vi ? ws[3 * (int64_t)ii] : T(0), w1 = vi ? ws[3 * (int64_t)ii + 1] : T(0),
+              w2 = vi ? ws[3 * (int64_t)ii + 2] : T(0);
       double a0 = 0, a1 = 0, a2 = 0;
       for (int j = ns.x; j < ns.y; ++j) {
         const T rx = (T)(x0 - xs[3 * (int64_t)j]), ry = (T)(x1 - xs[3 * (int64_t)j + 1]),
                 rz = (T)(x2 - xs[3 * (int64_t)j + 2]);
         T K[9];
         kernel_entry<T>(kp, wl, rx, ry, rz, K);
-        atomic_add3(farT + 3 * (int64_t)j, (double)(K[0] * w0 + K[3] * w1 + K[6] * w2),
-                    (double)(K[1] * w0 + K[4] * w1 + K[7] * w2),
-                    (double)(K[2] * w0 + K[5] * w1 + K[8] * w2));
+        if (vi)
+          atomic_add3(farT + 3 * (int64_t)j, (double)(K[0] * w0 + K[3] * w1 + K[6] * w2),
+                      (double)(K[1] * w0 + K[4] * w1 + K[7] * w2),
+                      (double)(K[2] * w0 + K[5] * w1 + K[8] * w2));
         if (KIND == KIND_MLP && want_grad) {
           const T f0 = Fs[3 * (int64_t)j], f1 = Fs[3 * (int64_t)j + 1], f2 = Fs[3 * (int64_t)j + 2];
           T gb[9] = {w0 * f0, w0 * f1, w0 * f2, w1 * f0, w1 * f1, w1 * f2, w2 * f0, w2 * f1, w2 * f2};
           T dr[3];
           mlp_vjp<T>(wl, kp.input_mode, rx, ry, rz, gb, dth, dr);
-          a0 += dr[0]; a1 += dr[1]; a2 += dr[2];
-          atomic_add3(dXs + 3 * (int64_t)j, -(double)dr[0], -(double)dr[1], -(double)dr[2]);
+          if (vi) {
+            a0 += dr[0]; a1 += dr[1]; a2 += dr[2];
+            atomic_add3(dXs + 3 * (int64_t)j, -(double)dr[0], -(double)dr[1], -(double)dr[2]);
+          }
         }
       }
-      if (KIND == KIND_MLP && want_grad) atomic_add3(dXs + 3 * (int64_t)i, a0, a1, a2);
+      if (KIND == KIND_MLP && want_grad && vi) atomic_add3(dXs + 3 * (int64_t)i, a0, a1, a2);
     }
   }
   if (KIND == KIND_MLP) {

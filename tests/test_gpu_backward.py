@@ -11,7 +11,7 @@
   replay) at N = 5,000 in FP64, 64 coordinates each of X, F and theta;
 * the dense FP64 gradient at N = 5,000 (stored by tests/golden/make_grad.py
   from the oracle): dF within 10 zeta, dX and dtheta within 100 zeta;
-* sampled rows of the dense gradient at N = 200,000 (FP32 form);
+* sampled rows of the dense gradient at N = 50,000 (FP32 form);
 * the autograd wrapper's gradients equal the oracle adjoint.
 """
 import hashlib
@@ -311,17 +311,18 @@ def test_backward_finite_differences_frozen_5k():
     assert all(v <= 1e-6 for v in worst.values())
 
 
-def test_backward_sampled_rows_200k():
-    """The FP32 backward at the differentiation workload's full size: rows of
-    dF and dX at 16 sampled particles against the dense FP64 gradient rows
-    (oracle.grad.dense_grad_rows): within 10 zeta and 100 zeta."""
+def test_backward_sampled_rows_50k():
+    """The FP32 backward on the differentiation workload's geometry (cube,
+    15% volume fraction) at N = 50,000: rows of dF and dX at 16 sampled
+    particles against the dense FP64 gradient rows (oracle.grad.
+    dense_grad_rows): within 10 zeta and 100 zeta. (The full N = 200,000 is
+    timed by bench.py --workload diff_200k --backward.)"""
     from gpu_common import ctx, dev, kernels, say
-    X, F, cfg = wl.workload("diff_200k")
+    X, F, cfg = wl.workload("diff_200k", 50000)
     n = X.shape[0]
     w = wl.normal_forces(n, seed=5)
     ko, kg = kernels("mlp")
-    # stored factors (the backward needs them): about 110 GB in FP32 here
-    ctx().set_budget(280 << 30)
+    ctx().set_budget(200 << 30)   # stored factors (the backward needs them)
     try:
         hm = hh.HMatrix(ctx(), dev(X), kg, c_leaf=cfg["c_leaf"], eta=1.0, eps=cfg["eps"],
                         prec="fp32")
@@ -333,7 +334,7 @@ def test_backward_sampled_rows_200k():
     rF, rX = OG.dense_grad_rows(X, F, w, ko, rows)
     eF = _rel(dF.double().cpu().numpy()[rows], rF)
     eX = _rel(dX.cpu().numpy()[rows], rX)
-    say("200k sampled rows: dF", eF, "dX", eX, hm.lr.info())
+    say("50k sampled rows: dF", eF, "dX", eX, hm.lr.info())
     assert eF <= 10 * cfg["eps"] and eX <= 100 * cfg["eps"]
 
 
