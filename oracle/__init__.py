@@ -24,5 +24,7 @@ Contents, each following the paper (arXiv 2505.08174) directly:
   grad       -- dense FP64 gradients of L = sum_i w_i . U_i with respect to F,
                 X and the MLP parameters, and the adjoint of the H-matrix
                 product with frozen structure
+  short      -- the short-range many-body terms M^(s,2) F + M^(t,3) F +
+                M^(s,3) F of Eq. (6) over neighbours and 3-cliques within R_cut
 """
-from . import kernels, dense, tree, partition, aca, hmatvec, grad  # noqa: F401
+from . import kernels, dense, tree, partition, aca, hmatvec, grad, short  # noqa: F401
