@@ -82,13 +82,18 @@ def alpha3(dj, dk, g: Net, r_cut: float = R_CUT):
 
 def neighbours(X, r_cut: float = R_CUT):
     """N(i) for every i: the particles j != i with |x_i - x_j| < r_cut (brute
-    force over all pairs), each list ascending."""
+    force over all pairs), each list ascending. The test is taken on squares
+    in FP64, (dx^2 + dy^2) + dz^2 < r_cut^2 with each operation rounded (no
+    fused multiply-add), so that a pair at the cut-off is decided the same way
+    by every implementation that follows this order."""
     X = np.asarray(X, dtype=np.float64)
     n = X.shape[0]
+    rc2 = float(r_cut) * float(r_cut)
     out = []
     for i in range(n):
-        d = np.sqrt(np.sum((X - X[i]) ** 2, axis=1))
-        nb = np.nonzero(d < r_cut)[0]
+        d = X - X[i]
+        d2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        nb = np.nonzero(d2 < rc2)[0]
         out.append(nb[nb != i])
     return out
 
