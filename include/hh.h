@@ -50,6 +50,7 @@ typedef struct hh_part_s* hh_part;
 typedef struct hh_lowrank_s* hh_lowrank;
 typedef struct hh_kernel_s* hh_kernel;
 typedef struct hh_batch_s* hh_batch;
+typedef struct hh_short_s* hh_short;
 
 typedef enum {
   HH_OK = 0,
@@ -304,6 +305,39 @@ hh_status hh_batch_info(hh_batch b, int64_t* n, int32_t* n_sys, int64_t* graph_n
                         int64_t* graph_launches, hh_tree* tree, hh_part* part, hh_lowrank* lr);
 void hh_batch_free(hh_batch b);
 
+/* ------------------------------------------ short-range many-body terms */
+
+/* Size of the packed parameter vector of the three-body network g:
+ * W1[64][6] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[18][64] b4[18]. */
+#define HH_G3_NPARAM 9938
+
+/* The remaining terms of Eq. (6), M^(s,2) F + M^(t,3) F + M^(s,3) F (Eq. (2)
+ * normalised as in Eq. (4)), over the neighbours N(i) within the cut-off
+ * r_cut (Sec. 2.2; 5 in Sec. 2.4) and the 3-cliques (j, k, i) with k in N(i),
+ * j in N(k), j != i (Sec. 2.3). With d_j = x_j - x_i, d_k = x_k - x_i:
+ *   alpha_2^(s) = sym(h_s(d_j / |d_j|)) / (8 pi |d_j|)         (times F_i)
+ *   alpha_3^(s), alpha_3^(t) = sym(g_s), sym(g_t) / (8 pi |x_j - x_k| |x_k - x_i|)
+ *                                                    (times F_i and F_j)
+ * where h_s is a 3-64-64-64-9 tanh MLP (s2_params: HH_MLP_NPARAM doubles, the
+ * layout of hh_kernel_create_mlp), g a 6-64-64-64-18 tanh MLP on
+ * (d_j, d_k) / r_cut whose outputs 0..8 and 9..17 are the row-major 3x3
+ * blocks g_s and g_t (g3_params: HH_G3_NPARAM doubles), sym(O) = (O + O^T)/2:
+ * seeded stand-ins for the trained networks.
+ * hh_short_create builds the neighbour lists of the tree's current positions
+ * (a uniform grid of cells of edge r_cut over the root box; a single-system
+ * tree only, else HH_ERR_INVALID_ARG; parameters are copied). The tree must
+ * outlive the handle. Syncs. */
+hh_status hh_short_create(hh_ctx ctx, hh_tree tree, const double* s2_params,
+                          const double* g3_params, double r_cut, hh_short* out);
+/* U += M^(s,2) F + M^(t,3) F + M^(s,3) F for the positions of the tree the
+ * handle was built on. F, U: device arrays in the caller's order with the
+ * types of hh_matvec for prec (the networks run on the VALU in FP64 for
+ * HH_FP64, FP32 otherwise, sums in FP64). Does not sync. */
+hh_status hh_short_matvec(hh_ctx ctx, hh_short s, hh_precision prec, const void* F, void* U);
+/* Neighbour pairs (sum of |N(i)|) and 3-cliques of the handle. */
+hh_status hh_short_info(hh_short s, int64_t* n_pairs, int64_t* n_cliques);
+void hh_short_free(hh_short s);
+
 /* ------------------------------------------------------- export and stats */
 
 /* Sizes of a tree: particles, nodes, leaves. Host outputs (nullable). */
@@ -350,6 +384,7 @@ hh_status hh_lowrank_factor(hh_lowrank l, int64_t b, int32_t k, double* ck, doub
 #define HH_PHASE_FAR 4       /* the t_k = Q_k F launch of hh_matvec */
 #define HH_PHASE_COMBINE 5   /* the combine/unpermute launch of hh_matvec */
 #define HH_PHASE_BACKWARD 6  /* the launches of hh_matvec_backward */
+#define HH_PHASE_SHORT 7     /* hh_short_create (whole call) and the hh_short_matvec launches */
 #define HH_NPHASE 8
 hh_status hh_ctx_set_profiling(hh_ctx ctx, int on);
 /* Accumulated milliseconds and event pairs per phase since the last reset

@@ -16,9 +16,10 @@ STATUS = {0: "HH_OK", 1: "HH_ERR_INVALID_ARG", 2: "HH_ERR_OUT_OF_MEMORY", 3: "HH
 HH_FP64, HH_FP32, HH_BF16, HH_BF16_SPLIT = 0, 1, 2, 3
 HH_MLP_INPUT_DIRECTION, HH_MLP_INPUT_DISPLACEMENT = 0, 1
 HH_MLP_NPARAM = 9161
+HH_G3_NPARAM = 9938
 LMAX_CAP = 64
 HH_NPHASE = 8
-PHASES = ("tree", "partition", "aca", "near", "far", "combine", "backward")
+PHASES = ("tree", "partition", "aca", "near", "far", "combine", "backward", "short")
 
 # name -> (restype, argtypes); every symbol declared in include/hh.h
 _vp, _i32, _i64, _d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
@@ -58,6 +59,10 @@ SIGNATURES = {
     "hh_batch_info": (C.c_int, [_vp, _pi64, _pi32, _pi64, _pi64, C.POINTER(_vp),
                                 C.POINTER(_vp), C.POINTER(_vp)]),
     "hh_batch_free": (None, [_vp]),
+    "hh_short_create": (C.c_int, [_vp, _vp, _pd, _pd, _d, C.POINTER(_vp)]),
+    "hh_short_matvec": (C.c_int, [_vp, _vp, C.c_int, _vp, _vp]),
+    "hh_short_info": (C.c_int, [_vp, _pi64, _pi64]),
+    "hh_short_free": (None, [_vp]),
     "hh_matvec": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int, _vp, _vp]),
     "hh_matvec_noalloc": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int, _vp, _vp]),
     "hh_matvec_backward": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int, _vp, _vp, _vp, _vp, _vp]),

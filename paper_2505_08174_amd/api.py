@@ -474,6 +474,37 @@ class Batch(_Handle):
         return U
 
 
+class ShortRange(_Handle):
+    """The short-range many-body terms M^(s,2) F + M^(t,3) F + M^(s,3) F of a
+    tree's current positions (hh_short_create); s2 and g3 are packed FP64
+    parameter vectors or (Ws, bs) lists of the two stand-in networks."""
+    _free = "hh_short_free"
+
+    def __init__(self, ctx: Context, tree: Tree, s2, g3, r_cut: float = 5.0):
+        p2 = pack_mlp(s2) if isinstance(s2, (tuple, list)) else np.ascontiguousarray(s2, np.float64)
+        p3 = pack_mlp(g3) if isinstance(g3, (tuple, list)) else np.ascontiguousarray(g3, np.float64)
+        assert p2.size == L.HH_MLP_NPARAM and p3.size == L.HH_G3_NPARAM
+        pd = C.POINTER(C.c_double)
+        h = C.c_void_p()
+        ctx.check(L.load().hh_short_create(ctx.h, tree.h, p2.ctypes.data_as(pd),
+                                           p3.ctypes.data_as(pd), float(r_cut), C.byref(h)))
+        super().__init__(ctx, h, keep=(tree,))
+        self.n = tree.info()[0]
+
+    def info(self):
+        a, b = C.c_int64(), C.c_int64()
+        self.ctx.check(L.load().hh_short_info(self.h, C.byref(a), C.byref(b)))
+        return {"n_pairs": a.value, "n_cliques": b.value}
+
+    def matvec(self, F: torch.Tensor, U: torch.Tensor, prec="fp64") -> torch.Tensor:
+        """U += M^(s,2) F + M^(t,3) F + M^(s,3) F (in place)."""
+        p = _prec(prec)
+        assert F.is_cuda and F.dtype == F_DTYPE[p] and F.is_contiguous() and F.shape == (self.n, 3)
+        assert U.dtype == U_DTYPE[p] and U.is_contiguous() and U.shape == F.shape
+        self.ctx.check(L.load().hh_short_matvec(self.ctx.h, self.h, p, _ptr(F), _ptr(U)))
+        return U
+
+
 def hmatvec(ctx, X, F, kern, c_leaf=64, eta=1.0, eps=1e-6, prec="fp64", l_max=48):
     """One full step: tree, partition, ACA and product."""
     return HMatrix(ctx, X, kern, c_leaf, eta, eps, prec, l_max) @ F
