@@ -26,5 +26,7 @@ Contents, each following the paper (arXiv 2505.08174) directly:
                 product with frozen structure
   short      -- the short-range many-body terms M^(s,2) F + M^(t,3) F +
                 M^(s,3) F of Eq. (6) over neighbours and 3-cliques within R_cut
+  stepping   -- gravity, filament tension and bending forces and the explicit
+                Euler step of Sec. 4.3
 """
-from . import kernels, dense, tree, partition, aca, hmatvec, grad, short  # noqa: F401
+from . import kernels, dense, tree, partition, aca, hmatvec, grad, short, stepping  # noqa: F401
