@@ -338,6 +338,30 @@ hh_status hh_short_matvec(hh_ctx ctx, hh_short s, hh_precision prec, const void*
 hh_status hh_short_info(hh_short s, int64_t* n_pairs, int64_t* n_cliques);
 void hh_short_free(hh_short s);
 
+/* --------------------------------------------------------- time stepping */
+
+/* Forces of a time step (Sec. 4.3): the uniform external force gravity
+ * (host, 3 values; (0, 0, -1) in Sec. 4.3.1) on every particle, plus the
+ * internal forces of n_fil filaments, each a chain of n_beads consecutive
+ * particles (chain c holds particles [c n_beads, (c + 1) n_beads) of X; the
+ * remaining particles are free), Sec. 4.3.2:
+ *   tension on every bond r = x_{i+1} - x_i: f = k_t (|r| - l0) r / |r|,
+ *     added to bead i and subtracted from bead i+1;
+ *   COS bending on every interior bead i: t_1, t_2 the unit bond vectors into
+ *     and out of i, T = -k_b (t_1 x t_2) |t_1 x t_2|, forces T x t_1 on i-1,
+ *     -T x t_2 on i+1 and minus their sum on i.
+ * X: device FP64 [n][3]; F: device [n][3], FP64 for HH_FP64, FP32 otherwise
+ * (the force type of hh_matvec), fully overwritten. n_fil * n_beads <= n,
+ * n_beads >= 2 when n_fil > 0, else HH_ERR_INVALID_ARG. Does not sync. */
+hh_status hh_filament_forces(hh_ctx ctx, const double* X, int64_t n, int64_t n_fil,
+                             int32_t n_beads, double k_t, double l0, double k_b,
+                             const double* gravity, hh_precision prec, void* F);
+/* Explicit Euler step of dX/dt = U (Sec. 4.3): X += dt U. X: device FP64
+ * [n][3], updated in place; U: device [n][3] of the type hh_matvec returns
+ * for prec (FP32 for HH_FP32, FP64 otherwise). Does not sync. */
+hh_status hh_euler_step(hh_ctx ctx, double* X, const void* U, int64_t n, double dt,
+                        hh_precision prec);
+
 /* ------------------------------------------------------- export and stats */
 
 /* Sizes of a tree: particles, nodes, leaves. Host outputs (nullable). */

@@ -63,6 +63,8 @@ SIGNATURES = {
     "hh_short_matvec": (C.c_int, [_vp, _vp, C.c_int, _vp, _vp]),
     "hh_short_info": (C.c_int, [_vp, _pi64, _pi64]),
     "hh_short_free": (None, [_vp]),
+    "hh_filament_forces": (C.c_int, [_vp, _vp, _i64, _i64, _i32, _d, _d, _d, _pd, C.c_int, _vp]),
+    "hh_euler_step": (C.c_int, [_vp, _vp, _vp, _i64, _d, C.c_int]),
     "hh_matvec": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int, _vp, _vp]),
     "hh_matvec_noalloc": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int, _vp, _vp]),
     "hh_matvec_backward": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int, _vp, _vp, _vp, _vp, _vp]),

@@ -11,6 +11,7 @@ from .gen import (  # noqa: F401
     lattice_sphere,
     lattice_cube,
     filament_chains,
+    filament_suspension,
     batch_workload,
     normal_forces,
     gravity_forces,

@@ -225,6 +225,69 @@ def filament_chains(n: int, phi: float, beads: int = 50, bond: float = 2.2,
     return pos.reshape(-1, 3)
 
 
+def filament_suspension(n_fil: int = 5120, n_beads: int = 21, bond: float = 3.0,
+                        n_free: int = 107520, min_dist: float = 2.1, seed: int = 0):
+    """A spherical cloud of straight filaments and free particles, the shape of
+    the flexible-filament workload of Sec. 4.3.2: outer radius
+    R_out = 4 * 10^(1/3) * (n_beads - 1) * bond; the filaments (n_beads beads
+    at spacing `bond`, random orientation) lie inside R_in = (1/2)^(1/3) R_out,
+    the free particles uniformly in the shell between R_in and R_out; no two
+    particles closer than min_dist (a candidate that clashes is drawn again).
+    Returns X with the filaments first (chain c = particles
+    [c n_beads, (c + 1) n_beads)), then the free particles."""
+    key = "filsusp_f%d_b%d_l%.6g_p%d_d%.6g_s%d" % (n_fil, n_beads, bond, n_free, min_dist, seed)
+    return _cached(key, lambda: _filament_suspension(n_fil, n_beads, bond, n_free, min_dist,
+                                                     seed))
+
+
+def _filament_suspension(n_fil, n_beads, bond, n_free, min_dist, seed):
+    r_out = 4.0 * 10.0 ** (1.0 / 3.0) * (n_beads - 1) * bond
+    r_in = 0.5 ** (1.0 / 3.0) * r_out
+    half = 0.5 * (n_beads - 1) * bond
+    rng = Rng(seed, "chain")
+    offs = (np.arange(n_beads) - 0.5 * (n_beads - 1)) * bond
+    placed = np.empty((0, 3))
+    chains = []
+    while len(chains) < n_fil:
+        m = n_fil - len(chains)
+        # centres uniform in the ball of radius r_in - half (so every bead is
+        # inside r_in), by rejection from the cube; directions uniform
+        c = (rng.uniform(3 * 2 * m).reshape(2 * m, 3) * 2.0 - 1.0) * (r_in - half)
+        c = c[np.sum(c * c, axis=1) <= (r_in - half) ** 2][:m]
+        d = rng.normal(3 * c.shape[0]).reshape(-1, 3)
+        d /= np.linalg.norm(d, axis=1)[:, None]
+        beads = c[:, None, :] + offs[None, :, None] * d[:, None, :]        # [m, nb, 3]
+        ok = np.ones(c.shape[0], dtype=bool)
+        if placed.shape[0]:
+            dist, _ = cKDTree(placed).query(beads.reshape(-1, 3), k=1)
+            ok &= ~np.any(dist.reshape(-1, n_beads) < min_dist, axis=1)
+        flat = beads.reshape(-1, 3)
+        pairs = cKDTree(flat).query_pairs(min_dist, output_type="ndarray")
+        for u, v in pairs.tolist():
+            cu, cv = u // n_beads, v // n_beads
+            if cu != cv and ok[min(cu, cv)]:
+                ok[max(cu, cv)] = False     # the later chain of a clashing pair is redrawn
+        for t in np.nonzero(ok)[0]:
+            chains.append(beads[t])
+        placed = np.concatenate([placed, beads[ok].reshape(-1, 3)])
+    rng2 = Rng(seed, "pos")
+    free = np.empty((0, 3))
+    while free.shape[0] < n_free:
+        m = 2 * (n_free - free.shape[0]) + 64
+        p = (rng2.uniform(3 * m).reshape(m, 3) * 2.0 - 1.0) * r_out
+        rr = np.sum(p * p, axis=1)
+        p = p[(rr <= r_out * r_out) & (rr >= r_in * r_in)]
+        allp = np.concatenate([placed, free])
+        dist, _ = cKDTree(allp).query(p, k=1)
+        p = p[dist >= min_dist]
+        keep = np.ones(p.shape[0], dtype=bool)
+        for u, v in cKDTree(p).query_pairs(min_dist, output_type="ndarray").tolist():
+            if keep[min(u, v)]:
+                keep[max(u, v)] = False
+        free = np.concatenate([free, p[keep]])[:n_free]
+    return np.concatenate([np.concatenate(chains)[: n_fil * n_beads], free])
+
+
 def normal_forces(n: int, seed: int = 0, scale: float = 1.0,
                   dtype=np.float64) -> np.ndarray:
     """F_i ~ N(0, scale^2 I3)."""
@@ -312,6 +375,11 @@ WORKLOADS = {
                       kernel="mlp", precision="fp32", c_leaf=128, eta=1.0, eps=1e-4),
     "diff_5k": dict(n=5000, geom="cube", phi=0.15, seed=0, forces="normal",
                     kernel="mlp", precision="fp32", c_leaf=128, eta=1.0, eps=1e-4),
+    # the flexible-filament suspension (5,120 chains of 21 beads, 107,520 free
+    # particles) under gravity with tension and bending, stepped in time
+    "filaments_215k": dict(n=215040, geom="filaments", phi=None, seed=0, forces="gravity",
+                           kernel="mlp", precision="bf16", c_leaf=128, eta=1.0, eps=0.02,
+                           n_fil=5120, n_beads=21, bond=3.0, dt=0.002, k_t=20.0, k_b=50.0),
     # 64 independent systems (batch_workload): n is the total, set when generated
     "batch64": dict(n=None, geom="batch", phi=None, seed=2, forces="normal",
                     kernel="mlp", precision="bf16", c_leaf=128, eta=1.0, eps=1e-4),
@@ -329,6 +397,12 @@ def workload(name: str, n: int | None = None):
         return X, F, w
     if n is not None:
         w["n"] = int(n)
+    if w["geom"] == "filaments":
+        # n (if given) scales both parts, keeping the equal split of Sec. 4.3.2
+        nf = max(1, int(round(w["n_fil"] * w["n"] / 215040)))
+        X = filament_suspension(nf, w["n_beads"], w["bond"], nf * w["n_beads"], seed=w["seed"])
+        w["n_fil"], w["n"] = nf, int(X.shape[0])
+        return X, np.tile([0.0, 0.0, -1.0], (X.shape[0], 1)), w
     if w["geom"] == "cube":
         X = rsa_cube(w["n"], w["phi"], seed=w["seed"])
     else:
