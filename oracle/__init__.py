@@ -28,5 +28,9 @@ Contents, each following the paper (arXiv 2505.08174) directly:
                 M^(s,3) F of Eq. (6) over neighbours and 3-cliques within R_cut
   stepping   -- gravity, filament tension and bending forces and the explicit
                 Euler step of Sec. 4.3
+  rotation   -- the 6N mobility of Eq. (1) with torques and rotational
+                velocities (Rotne-Prager rotational blocks), dense and as the
+                H-matrix over its grid of 3x3 entries
 """
 from . import kernels, dense, tree, partition, aca, hmatvec, grad, short, stepping  # noqa: F401
+from . import rotation  # noqa: F401
