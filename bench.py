@@ -176,7 +176,10 @@ def cpu_baseline(X, F, kern_cfg, U_gpu, budget_s):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         threads = os.cpu_count() or 1
-    if kern_cfg["kernel"] == "rpy":
+    if kern_cfg["kernel"] == "rpy6":
+        from oracle import rotation as OR
+        ko = None
+    elif kern_cfg["kernel"] == "rpy":
         ko = OK.Kernel("rpy")
     else:
         ko = OK.Kernel("mlp", OK.MLP(*wl.mlp_weights(1)))
@@ -186,7 +189,10 @@ def cpu_baseline(X, F, kern_cfg, U_gpu, budget_s):
     got, t0 = [], time.perf_counter()
     ref = []
     for r in rows:
-        if off is None:
+        if ko is None:   # the 6N product: (U_i, w_i)
+            U6, W6 = OR.u6(X, F[:, :3], F[:, 3:], rows=np.array([r]))
+            ref.append(np.concatenate([U6[0], W6[0]]))
+        elif off is None:
             ref.append(OD.dense_u(X, F, ko, np.array([r]))[0])
         else:   # the dense sum over the row's own system
             s = int(np.searchsorted(off, r, side="right") - 1)
@@ -225,8 +231,15 @@ def main():
     prec = a.prec or cfg["precision"]
     n = X.shape[0]
     log("workload %s n=%d prec=%s" % (a.workload, n, prec))
+    six = cfg["kernel"] == "rpy6"
+    if six and (a.short or a.backward or a.autotune):
+        print("the 6N workload runs the product alone (no --short, --backward or --autotune)",
+              file=sys.stderr)
+        sys.exit(2)
     ctx = hh.Context(0)
-    if cfg["kernel"] == "rpy":
+    if six:
+        kern = hh.Kernel.rpy6(ctx)
+    elif cfg["kernel"] == "rpy":
         kern = hh.Kernel.rpy(ctx)
     else:
         kern = hh.Kernel.mlp(ctx, wl.mlp_weights(1), "direction")
@@ -284,7 +297,9 @@ def main():
         if sus is not None:
             U = sus.step()
             return U, sus.hm.tree, sus.hm.part, sus.hm.lr
-        if offsets is None:
+        if six:
+            t = hh.build_tree6(ctx, Xd, c_leaf)
+        elif offsets is None:
             t = hh.build_tree(ctx, Xd, c_leaf)
         else:
             t = hh.build_tree_batch(ctx, Xd, offsets, c_leaf)
@@ -319,7 +334,8 @@ def main():
     nG, nH = p.info()
     ps = p.stats()
     li = lr.info()
-    pairs_near = ps["near_pairs"] - n          # self pairs are skipped
+    # self pairs are skipped (a particle's 2 x 2 row pairs for the 6N kernel)
+    pairs_near = ps["near_pairs"] - (4 * n if six else n)
     per_step = {k: v[0] / a.steps for k, v in ph.items()}
     log("phases ms/step:", {k: round(v, 3) for k, v in per_step.items()})
     # dominant kernel: kernel queries (pairs) per launch x the MLP's flops

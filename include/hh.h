@@ -125,6 +125,21 @@ hh_status hh_kernel_create_rpy(hh_ctx ctx, double a, double mu, hh_kernel* out);
  * mobility is 1/(6 pi mu a). */
 hh_status hh_kernel_create_mlp(hh_ctx ctx, const double* params, int input_mode, double a,
                                double mu, hh_kernel* out);
+/* The 6N mobility with rotations, [U; w] = M [F; T] of Eq. (1), with the
+ * Rotne-Prager blocks for spheres of radius a in a fluid of viscosity mu
+ * (r = x_i - x_j, d = |r|, [r]_x u = r x u):
+ *   U from F: the RPY tensor of hh_kernel_create_rpy, self 1/(6 pi mu a) I;
+ *   w from F and U from T: -[r]_x / (8 pi mu d^3) (the same function of r in
+ *                          both places), self 0;
+ *   w from T: -(I - 3 r r^T / d^2) / (16 pi mu d^3), self 1/(8 pi mu a^3) I.
+ * The rotational blocks are the non-overlapping forms (d >= 2a); the
+ * translational block is the full RPY tensor. The paper limits itself to
+ * translation and names this extension (end of Sec. 2.2). The kernel works
+ * on the 2n rows of a tree from hh_build_tree6 (and only there): each 3x3
+ * entry of the 6N matrix is one ACA entry (Algorithm 2 as for 3N), with the
+ * |det| pivot magnitude in every precision (the translation-rotation entries
+ * are singular). HH_FP64 and HH_FP32 only; no backward. Requires a, mu > 0. */
+hh_status hh_kernel_create_rpy6(hh_ctx ctx, double a, double mu, hh_kernel* out);
 void hh_kernel_free(hh_kernel k);
 
 /* ----------------------------------------------------------- the hot path */
@@ -138,6 +153,19 @@ void hh_kernel_free(hh_kernel k);
  * HH_ERR_INVALID_ARG; two identical positions -> HH_ERR_DUPLICATE_POINTS.
  * Syncs. */
 hh_status hh_build_tree(hh_ctx ctx, const double* X, int64_t n, int32_t c_leaf, hh_tree* out);
+
+/* Tree of the 6N mobility: the cluster tree of hh_build_tree on the n
+ * particles X (c_leaf counts particles), with every particle's two rows
+ * (2i: translation and force, 2i + 1: rotation and torque) next to each other,
+ * so the tree has 2n rows, every cluster twice its particles' rows and the
+ * same boxes and nodes. hh_partition, hh_aca_build and hh_matvec then work on
+ * it with hh_kernel_create_rpy6; hh_matvec takes F as [n][6] = (F_i, T_i)
+ * and returns U as [n][6] = (U_i, w_i). hh_tree_info reports 2n rows and
+ * hh_tree_export their permutation (row 2p + r of the sorted order is input
+ * row 2 perm[p] + r); hh_tree_refit takes the n particle positions. Not for
+ * hh_short_create or batched trees. Errors as hh_build_tree with n < 2^30 - 1.
+ * Syncs. */
+hh_status hh_build_tree6(hh_ctx ctx, const double* X, int64_t n, int32_t c_leaf, hh_tree* out);
 
 /* Many independent systems in one tree (the batched form): X is the
  * concatenation of n_sys systems, offsets (host, n_sys + 1 values, offsets[0]
@@ -159,7 +187,8 @@ hh_status hh_build_tree_batch_leaf(hh_ctx ctx, const double* X, const int64_t* o
 /* New positions for an existing tree, keeping its particle order, nodes and
  * leaves (Definition 1's clusters as index sets) and recomputing the sorted
  * positions and the tight boxes of every node. X: device FP64 [n][3] in the
- * caller's order. The Morton keys are not recomputed, and a partition built
+ * caller's order (for a tree of hh_build_tree6: the n particles, not its 2n
+ * rows). The Morton keys are not recomputed, and a partition built
  * on the tree keeps its blocks (Eq. (7) is not re-tested). Used to evaluate
  * the frozen-structure product at perturbed positions (finite differences
  * of hh_matvec_backward) and for time steps that keep the structure.

@@ -43,9 +43,11 @@ SIGNATURES = {
     "hh_ctx_set_budget": (C.c_int, [_vp, C.c_size_t]),
     "hh_ctx_set_team_min": (C.c_int, [_vp, C.c_int32]),
     "hh_kernel_create_rpy": (C.c_int, [_vp, _d, _d, C.POINTER(_vp)]),
+    "hh_kernel_create_rpy6": (C.c_int, [_vp, _d, _d, C.POINTER(_vp)]),
     "hh_kernel_create_mlp": (C.c_int, [_vp, _pd, C.c_int, _d, _d, C.POINTER(_vp)]),
     "hh_kernel_free": (None, [_vp]),
     "hh_build_tree": (C.c_int, [_vp, _vp, _i64, _i32, C.POINTER(_vp)]),
+    "hh_build_tree6": (C.c_int, [_vp, _vp, _i64, _i32, C.POINTER(_vp)]),
     "hh_build_tree_batch": (C.c_int, [_vp, _vp, _pi64, _i32, _i32, C.POINTER(_vp)]),
     "hh_build_tree_batch_leaf": (C.c_int, [_vp, _vp, _pi64, _i32, C.POINTER(_i32),
                                            C.POINTER(_vp)]),

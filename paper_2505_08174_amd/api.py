@@ -101,6 +101,16 @@ class Kernel(_Handle):
         return k
 
     @staticmethod
+    def rpy6(ctx: Context, a: float = 1.0, mu: float = 1.0):
+        """The 6N mobility with rotations (forces and torques); goes with
+        build_tree6."""
+        h = C.c_void_p()
+        ctx.check(L.load().hh_kernel_create_rpy6(ctx.h, a, mu, C.byref(h)))
+        k = Kernel(ctx, h)
+        k.kind, k.a, k.mu = "rpy6", a, mu
+        return k
+
+    @staticmethod
     def mlp(ctx: Context, params, input_mode: str = "direction", a: float = 1.0, mu: float = 1.0):
         """params: packed FP64 vector (W1,b1,...,W4,b4) or (Ws, bs) lists."""
         p = pack_mlp(params) if isinstance(params, (tuple, list)) else np.ascontiguousarray(
@@ -206,6 +216,18 @@ def build_tree(ctx: Context, X: torch.Tensor, c_leaf: int) -> Tree:
     return Tree(ctx, h)
 
 
+def build_tree6(ctx: Context, X: torch.Tensor, c_leaf: int) -> Tree:
+    """Tree of the 2n rows (translation, rotation of every particle) of the
+    6N mobility; c_leaf counts particles."""
+    assert X.is_cuda and X.dtype == torch.float64 and X.dim() == 2 and X.shape[1] == 3
+    X = X.contiguous()
+    h = C.c_void_p()
+    ctx.check(L.load().hh_build_tree6(ctx.h, _ptr(X), X.shape[0], int(c_leaf), C.byref(h)))
+    t = Tree(ctx, h)
+    t.six = True
+    return t
+
+
 def build_tree_batch(ctx: Context, X: torch.Tensor, offsets, c_leaf) -> Tree:
     """One tree over several independent systems (concatenated in X); c_leaf
     is one leaf size or one per system."""
@@ -269,7 +291,8 @@ def aca_build_pivots(ctx: Context, tree: Tree, part: Partition, kern: Kernel, pr
 
 def tree_refit(ctx: Context, tree: Tree, X: torch.Tensor) -> Tree:
     """New positions for `tree`, keeping its order and nodes (in place)."""
-    assert X.is_cuda and X.dtype == torch.float64 and X.shape == (tree.info()[0], 3)
+    rows = tree.info()[0] // (2 if getattr(tree, "six", False) else 1)
+    assert X.is_cuda and X.dtype == torch.float64 and X.shape == (rows, 3)
     X = X.contiguous()
     ctx.check(L.load().hh_tree_refit(ctx.h, tree.h, _ptr(X)))
     return tree
@@ -278,7 +301,9 @@ def tree_refit(ctx: Context, tree: Tree, X: torch.Tensor) -> Tree:
 def matvec(ctx: Context, tree: Tree, part: Partition, lr: LowRank, kern: Kernel, F: torch.Tensor,
            prec="fp64", U: torch.Tensor | None = None) -> torch.Tensor:
     p = _prec(prec)
-    assert F.is_cuda and F.dtype == F_DTYPE[p] and F.shape == (tree.info()[0], 3)
+    # [n][3], or [n/2][6] = (F_i, T_i) on a tree of build_tree6
+    assert F.is_cuda and F.dtype == F_DTYPE[p] and F.numel() == 3 * tree.info()[0]
+    assert F.shape[-1] == (6 if getattr(tree, "six", False) else 3)
     F = F.contiguous()
     if U is None:
         U = torch.empty(F.shape, dtype=U_DTYPE[p], device=F.device)
@@ -293,6 +318,7 @@ def matvec_noalloc(ctx: Context, tree: Tree, part: Partition, lr: LowRank, kern:
     library's static device scratch (U must be given: nothing is allocated)."""
     p = _prec(prec)
     assert F.is_cuda and F.dtype == F_DTYPE[p] and F.is_contiguous()
+    assert F.numel() == 3 * tree.info()[0]
     assert U.dtype == U_DTYPE[p] and U.is_contiguous() and U.shape == F.shape
     ctx.check(L.load().hh_matvec_noalloc(ctx.h, tree.h, part.h, lr.h, kern.h, p, _ptr(F),
                                          _ptr(U)))
@@ -364,7 +390,10 @@ class HMatrix:
     def __init__(self, ctx, X, kern, c_leaf=64, eta=1.0, eps=1e-6, prec="fp64", l_max=48,
                  dense_mode=False, offsets=None):
         self.ctx, self.kern, self.prec = ctx, kern, _prec(prec)
-        if offsets is None:
+        if getattr(kern, "kind", None) == "rpy6":
+            assert offsets is None
+            self.tree = build_tree6(ctx, X, c_leaf)
+        elif offsets is None:
             self.tree = build_tree(ctx, X, c_leaf)
         else:
             self.tree = build_tree_batch(ctx, X, offsets, c_leaf)

@@ -14,7 +14,9 @@
 // Pivot magnitude: squared Frobenius norm in the FP64 form (Algorithm 2);
 // |det| of the 3x3 entry in the FP32 and BF16 forms (the magnitude the text
 // around Eq. (9) names), which avoids nearly singular pivots whose inverse
-// would amplify single-precision rounding in c_k = a P^-1.
+// would amplify single-precision rounding in c_k = a P^-1. The 6N kernel
+// takes |det| in every form: its translation-rotation entries are singular
+// (antisymmetric 3x3), and the Frobenius rule would pick them as pivots.
 // Guards: a residual column with ||a||^2 <= 1e-30 lambda^2 ends as converged
 // without a new term; |det P| <= 1e-14 ||P||_F^3 ends with a dense fallback;
 // l_max terms without convergence end with a dense fallback.
@@ -468,7 +470,7 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
               for (int e = 0; e < 9; ++e) rs[r][e] = Ck[9 * (int64_t)i + e];
             } else {
               kernel_entry<T>(a.kp, wl, (T)(xt[3 * i] - yj0), (T)(xt[3 * i + 1] - yj1),
-                              (T)(xt[3 * i + 2] - yj2), rs[r]);
+                              (T)(xt[3 * i + 2] - yj2), rs[r], i & 1, j & 1);
             }
           } else {
 #pragma unroll
@@ -675,7 +677,7 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
               for (int e = 0; e < 9; ++e) rs[r][e] = Qk[9 * (int64_t)jj + e];
             } else {
               kernel_entry<T>(a.kp, wl, (T)(xi0 - xsr[3 * jj]), (T)(xi1 - xsr[3 * jj + 1]),
-                              (T)(xi2 - xsr[3 * jj + 2]), rs[r]);
+                              (T)(xi2 - xsr[3 * jj + 2]), rs[r], ik & 1, jj & 1);
             }
           } else {
 #pragma unroll
@@ -826,7 +828,7 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
         for (int jj = 0; jj < q; ++jj) {
           T K[9];
           kernel_entry<T>(a.kp, wl, (T)(x0 - xsr[3 * jj]), (T)(x1 - xsr[3 * jj + 1]),
-                          (T)(x2 - xsr[3 * jj + 2]), K);
+                          (T)(x2 - xsr[3 * jj + 2]), K, i & 1, jj & 1);
           const T* f = a.Fs + 3 * ((int64_t)ns.x + jj);
           v0 += K[0] * f[0] + K[1] * f[1] + K[2] * f[2];
           v1 += K[3] * f[0] + K[4] * f[1] + K[5] * f[2];
@@ -954,7 +956,7 @@ void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
   a.ublk = ublk;
   a.uoff = uoff;
   a.frags = k->pbf.as<uint4>();
-  a.det_pivot = lr->prec != HH_FP64;
+  a.det_pivot = lr->prec != HH_FP64 || k->kind == KIND_RPY6;
   const int64_t nb = b1 - b0;
   if (nb <= 0) return;
   // persistent grid: as many workgroups as stay resident, each wave a worker

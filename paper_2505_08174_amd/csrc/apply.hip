@@ -114,7 +114,7 @@ __global__ __launch_bounds__(T256) void k_combine(
         for (int j = ns.x; j < ns.y; ++j) {
           T K[9];
           kernel_entry<T>(kp, wl, (T)(x0 - xs[3 * (int64_t)j]), (T)(x1 - xs[3 * (int64_t)j + 1]),
-                          (T)(x2 - xs[3 * (int64_t)j + 2]), K);
+                          (T)(x2 - xs[3 * (int64_t)j + 2]), K, (int)(s & 1), j & 1);
           T f0 = Fs[3 * (int64_t)j], f1 = Fs[3 * (int64_t)j + 1], f2 = Fs[3 * (int64_t)j + 2];
           v0 += K[0] * f0 + K[1] * f1 + K[2] * f2;
           v1 += K[3] * f0 + K[4] * f1 + K[5] * f2;
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(T256) void k_combine(
       }
     }
   }
-  const double a1 = kp.alpha1;
+  const double a1 = (s & 1) ? kp.alpha2 : kp.alpha1;
   u0 += a1 * (double)Fs[3 * s];
   u1 += a1 * (double)Fs[3 * s + 1];
   u2 += a1 * (double)Fs[3 * s + 2];
@@ -175,13 +175,14 @@ template <class T, class TU, class TO>
 __global__ __launch_bounds__(T256) void k_final(int64_t n, const int32_t* __restrict__ perm,
                                                 const T* __restrict__ Fs, const TU* __restrict__ Un,
                                                 const double* __restrict__ Uf, double alpha1,
-                                                TO* __restrict__ U) {
+                                                double alpha2, TO* __restrict__ U) {
   int64_t s = (int64_t)blockIdx.x * T256 + threadIdx.x;
   if (s >= n) return;
   const int64_t o = perm[s];
+  const double a1 = (s & 1) ? alpha2 : alpha1;   // odd rows: rotational rows of a 6N kernel
 #pragma unroll
   for (int d = 0; d < 3; ++d)
-    U[3 * o + d] = (TO)(((double)Un[3 * s + d] + Uf[3 * s + d]) + alpha1 * (double)Fs[3 * s + d]);
+    U[3 * o + d] = (TO)(((double)Un[3 * s + d] + Uf[3 * s + d]) + a1 * (double)Fs[3 * s + d]);
 }
 
 // Stored mode. Fs_ws and Un_ws hold the sorted forces (3 n T) and the
@@ -291,7 +292,7 @@ void matvec_streamed_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kerne
     PhaseTimer timer(ctx, HH_PHASE_COMBINE);
     hipLaunchKernelGGL((k_final<T, TU, TO>), dim3(nblk(n)), dim3(T256), 0, st, n,
                        t->perm.as<int32_t>(), Fs.as<T>(), Un.as<TU>(), Uf.as<double>(),
-                       k->alpha1, (TO*)U);
+                       k->alpha1, k->alpha2, (TO*)U);
   }
   HIP_OK(hipGetLastError());
   lr->stats_dirty = true;
@@ -308,6 +309,9 @@ hh_status hh_aca_build(hh_ctx ctx, hh_tree tree, hh_part part, hh_kernel kern,
   HH_API_BEGIN(ctx)
   HH_REQUIRE(out && tree && part && kern, HH_ERR_INVALID_ARG, "NULL argument");
   HH_REQUIRE(part->tree == tree, HH_ERR_INVALID_ARG, "partition was built on another tree");
+  check_kernel_tree(tree, kern);
+  HH_REQUIRE(kern->kind != KIND_RPY6 || prec == HH_FP64 || prec == HH_FP32, HH_ERR_INVALID_ARG,
+             "the 6N kernel runs in HH_FP64 and HH_FP32");
   if (freeze_pivots_from) {
     // the recursion replayed with the pivots, ranks and fallbacks of an
     // earlier build on the same partition (eps and l_max unused)

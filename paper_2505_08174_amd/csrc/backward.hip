@@ -750,6 +750,8 @@ extern "C" hh_status hh_matvec_backward(hh_ctx ctx, hh_tree tree, hh_part part, 
              "the backward needs stored factors (raise the budget with hh_ctx_set_budget)");
   HH_REQUIRE(!(dX || dparams) || kern->kind == KIND_MLP, HH_ERR_INVALID_ARG,
              "dX and dparams need the MLP kernel");
+  HH_REQUIRE(kern->kind != KIND_RPY6, HH_ERR_INVALID_ARG,
+             "the backward takes the 3N kernels (the 6N matrix is symmetric: dF = M dU)");
   PhaseTimer timer(ctx, HH_PHASE_BACKWARD);
   if (prec == HH_FP64)
     backward_t<double>(ctx, tree, part, lr, kern, F, dU, dF, dX, dparams);

@@ -56,6 +56,7 @@ hh_status hh_batch_create(hh_ctx ctx, const double* X, const hh_batch_params* pr
   HH_API_BEGIN(ctx)
   HH_REQUIRE(out && X && prm && kern, HH_ERR_INVALID_ARG, "NULL argument");
   HH_REQUIRE(prm->n_sys >= 1 && prm->offsets, HH_ERR_INVALID_ARG, "n_sys >= 1 and offsets needed");
+  HH_REQUIRE(kern->kind != KIND_RPY6, HH_ERR_INVALID_ARG, "batched products take the 3N kernels");
   HH_REQUIRE(prm->prec == HH_FP64 || prm->prec == HH_FP32 || is_bf16(prm->prec),
              HH_ERR_INVALID_ARG, "unknown precision");
   hh_batch_s* b = new hh_batch_s();

@@ -89,6 +89,7 @@ KParams make_kparams(hh_kernel k, bool fp64) {
   kp.c8 = 1.0 / (8.0 * HH_PI * k->mu);
   kp.c6 = 1.0 / (6.0 * HH_PI * k->mu * k->a);
   kp.alpha1 = k->alpha1;
+  kp.alpha2 = k->alpha2;
   kp.w = fp64 ? k->p64.p : k->p32.p;
   return kp;
 }
@@ -353,6 +354,24 @@ hh_status hh_kernel_create_rpy(hh_ctx ctx, double a, double mu, hh_kernel* out) 
   k->a = a;
   k->mu = mu;
   k->alpha1 = 1.0 / (6.0 * M_PI * mu * a);
+  k->alpha2 = k->alpha1;
+  *out = k;
+  HH_API_END(ctx)
+}
+
+hh_status hh_kernel_create_rpy6(hh_ctx ctx, double a, double mu, hh_kernel* out) {
+  if (out) *out = nullptr;
+  HH_API_BEGIN(ctx)
+  HH_REQUIRE(out, HH_ERR_INVALID_ARG, "out is NULL");
+  HH_REQUIRE(a > 0 && mu > 0 && isfinite(a) && isfinite(mu), HH_ERR_INVALID_ARG,
+             "RPY kernel needs a > 0 and mu > 0");
+  hh_kernel k = new hh_kernel_s();
+  k->ctx = ctx;
+  k->kind = KIND_RPY6;
+  k->a = a;
+  k->mu = mu;
+  k->alpha1 = 1.0 / (6.0 * M_PI * mu * a);
+  k->alpha2 = 1.0 / (8.0 * M_PI * mu * a * a * a);
   *out = k;
   HH_API_END(ctx)
 }
@@ -375,6 +394,7 @@ hh_status hh_kernel_create_mlp(hh_ctx ctx, const double* params, int input_mode,
     k->a = a;
     k->mu = mu;
     k->alpha1 = 1.0 / (6.0 * M_PI * mu * a);
+    k->alpha2 = k->alpha1;
     k->host_params.assign(params, params + MLP_NP);
     std::vector<float> p32(params, params + MLP_NP);
     std::vector<uint16_t> fr = build_bf16_frags(params);

@@ -87,6 +87,46 @@ __device__ __forceinline__ void rpy_entry(T rx, T ry, T rz, T a, T c8, T c6, T K
   K[6] = K[2];             K[7] = K[5];             K[8] = ci + s * rz * rz;
 }
 
+// The 6N Rotne-Prager mobility on its grid of 3x3 entries (Eq. (1)): row
+// parity si = 0 is a translational velocity, 1 a rotational one; column
+// parity sj = 0 a force, 1 a torque. r = x_i - x_j, d = |r|, c8 = 1/(8 pi mu):
+//   (0, 0): the RPY tensor above;
+//   (1, 0) and (0, 1): -(c8 / d^3) [r]_x, [r]_x u = r x u (half the curl of
+//           the Stokeslet flow; the coupling block is the same function of r
+//           in both places);
+//   (1, 1): -(c8 / (2 d^3)) (I - 3 r r^T / d^2) (half the curl of the rotlet
+//           flow).
+// The rotational blocks are the forms for non-overlapping spheres (d >= 2a).
+// d = 0 (the two rows of one particle) gives zeros: the self terms are added
+// separately.
+template <class T>
+__device__ __forceinline__ void rpy6_entry(int si, int sj, T rx, T ry, T rz, T a, T c8, T c6,
+                                           T K[9]) {
+  if ((si | sj) == 0) {
+    rpy_entry<T>(rx, ry, rz, a, c8, c6, K);
+    return;
+  }
+  const T d2 = rx * rx + ry * ry + rz * rz;
+  if (!(d2 > T(0))) {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) K[e] = T(0);
+    return;
+  }
+  const T id2 = T(1) / d2;
+  const T id3 = id2 * sqrt(id2);
+  if (si != sj) {
+    const T s = c8 * id3;
+    K[0] = T(0);   K[1] = s * rz;  K[2] = -s * ry;
+    K[3] = -s * rz; K[4] = T(0);   K[5] = s * rx;
+    K[6] = s * ry;  K[7] = -s * rx; K[8] = T(0);
+  } else {
+    const T ci = -T(0.5) * c8 * id3, co = T(1.5) * c8 * id3 * id2;
+    K[0] = ci + co * rx * rx; K[1] = co * rx * ry;      K[2] = co * rx * rz;
+    K[3] = K[1];              K[4] = ci + co * ry * ry; K[5] = co * ry * rz;
+    K[6] = K[2];              K[7] = K[5];              K[8] = ci + co * rz * rz;
+  }
+}
+
 // ------------------------------------------------------------- MLP (VALU)
 
 // Raw outputs o[9] of the 3-64-64-64-9 tanh MLP at input v, parameters packed
@@ -143,7 +183,9 @@ __device__ __forceinline__ void mlp_entry(const PT* __restrict__ P, int input_mo
 struct KParams {
   int kind;
   int input_mode;
-  double a, c8, c6, alpha1;
+  // alpha1: self mobility of even rows; alpha2: of odd rows (the rotational
+  // rows of a 6N kernel; equal to alpha1 for the 3N kernels)
+  double a, c8, c6, alpha1, alpha2;
   const void* w;     // packed MLP parameters (double or float per T)
 };
 
@@ -151,13 +193,23 @@ struct KParams {
 // (fp64) or the FP32 copy.
 KParams make_kparams(hh_kernel k, bool fp64);
 
+// Entry K(r) between rows i and j; si, sj are their parities (i & 1, j & 1),
+// which only the 6N kernel reads.
 template <class T>
 __device__ __forceinline__ void kernel_entry(const KParams& kp, const T* __restrict__ wl, T rx,
-                                             T ry, T rz, T K[9]) {
+                                             T ry, T rz, T K[9], int si = 0, int sj = 0) {
   if (kp.kind == KIND_RPY)
     rpy_entry<T>(rx, ry, rz, T(kp.a), T(kp.c8), T(kp.c6), K);
+  else if (kp.kind == KIND_RPY6)
+    rpy6_entry<T>(si, sj, rx, ry, rz, T(kp.a), T(kp.c8), T(kp.c6), K);
   else
     mlp_entry<T, T>(wl, kp.input_mode, rx, ry, rz, K);
+}
+
+// Rows i and j belong to one particle (their pair term is not summed): the
+// same row, or for the 6N kernel the two rows 2p, 2p + 1 of particle p.
+__device__ __forceinline__ bool same_particle(int kind, int64_t i, int64_t j) {
+  return kind == KIND_RPY6 ? (i >> 1) == (j >> 1) : i == j;
 }
 
 // ------------------------------------------------------- wave reductions

@@ -92,7 +92,10 @@ struct PhaseTimer {
 
 // --------------------------------------------------------------- the kernel
 
-enum { KIND_RPY = 0, KIND_MLP = 1 };
+// KIND_RPY6: the 6N Rotne-Prager mobility with rotations, on a tree whose
+// rows are the 2n generalized rows (2i: translation / force of particle i,
+// 2i + 1: rotation / torque)
+enum { KIND_RPY = 0, KIND_MLP = 1, KIND_RPY6 = 2 };
 
 struct hh_kernel_s {
   hh_ctx ctx = nullptr;
@@ -100,6 +103,7 @@ struct hh_kernel_s {
   int input_mode = HH_MLP_INPUT_DIRECTION;
   double a = 1.0, mu = 1.0;
   double alpha1 = 0.0;
+  double alpha2 = 0.0;              // self mobility of odd rows (= alpha1 but for KIND_RPY6)
   std::vector<double> host_params;  // MLP, packed (HH_MLP_NPARAM)
   DevBuf p64;                       // MLP params FP64, packed
   DevBuf p32;                       // MLP params FP32, packed
@@ -142,7 +146,16 @@ struct hh_tree_s {
   std::vector<int64_t> offs_host;   // particle offsets of the systems [n_sys+1]
   DevBuf offs;                      // same, on the device
   DevBuf roots;                     // int32 [n_sys] root node of each system
+  // the rows are the 2 n_particles generalized rows of the 6N mobility
+  // (n = 2 n_particles; sorted row 2p + s is row s of sorted particle p)
+  bool six = false;
 };
+
+// A tree of generalized rows goes with the 6N kernel and only with it.
+inline void check_kernel_tree(hh_tree t, hh_kernel k) {
+  HH_REQUIRE(t->six == (k->kind == KIND_RPY6), HH_ERR_INVALID_ARG,
+             "the 6N kernel needs a tree from hh_build_tree6, and such a tree the 6N kernel");
+}
 
 // ------------------------------------------------------------ the partition
 

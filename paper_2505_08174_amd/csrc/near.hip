@@ -58,11 +58,11 @@ __global__ __launch_bounds__(NEAR_T) void k_near_valu(NearArgs<T> a) {
         __syncthreads();
         if (act) {
           for (int jj = 0; jj < cnt; ++jj) {
-            if (jb + jj == i) continue;
+            if (same_particle(a.kp.kind, jb + jj, i)) continue;
             T rx = (T)(a.sgn * (xi0 - sx[3 * jj])), ry = (T)(a.sgn * (xi1 - sx[3 * jj + 1])),
               rz = (T)(a.sgn * (xi2 - sx[3 * jj + 2]));
             T K[9];
-            kernel_entry<T>(a.kp, wl, rx, ry, rz, K);
+            kernel_entry<T>(a.kp, wl, rx, ry, rz, K, i & 1, (jb + jj) & 1);
             T f0 = sf[3 * jj], f1 = sf[3 * jj + 1], f2 = sf[3 * jj + 2];
             u0 += K[0] * f0 + K[1] * f1 + K[2] * f2;
             u1 += K[3] * f0 + K[4] * f1 + K[5] * f2;
@@ -97,6 +97,7 @@ void launch_near_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void* Fs
   a.kp.c8 = 1.0 / (8.0 * HH_PI * k->mu);
   a.kp.c6 = 1.0 / (6.0 * HH_PI * k->mu * k->a);
   a.kp.alpha1 = k->alpha1;
+  a.kp.alpha2 = k->alpha2;
   a.kp.w = sizeof(T) == 8 ? k->p64.p : k->p32.p;
   a.n_leaves = t->n_leaves;
   if (k->kind == KIND_MLP)

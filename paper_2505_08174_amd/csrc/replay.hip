@@ -76,7 +76,7 @@ __global__ __launch_bounds__(TB) void k_aca_replay(const int2* __restrict__ G, i
       for (int i = threadIdx.x; i < c; i += TB) {
         T rs[9];
         kernel_entry<T>(kp, wl, (T)(xt[3 * i] - y0), (T)(xt[3 * i + 1] - y1),
-                        (T)(xt[3 * i + 2] - y2), rs);
+                        (T)(xt[3 * i + 2] - y2), rs, i & 1, jk & 1);
         for (int m = 0; m < k; ++m) {
           T cv[9];
           const T* cm = pool + fp[m] + 9 * (int64_t)i;
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(TB) void k_aca_replay(const int2* __restrict__ G, i
       for (int j = threadIdx.x; j < q; j += TB) {
         T rs[9];
         kernel_entry<T>(kp, wl, (T)(x0 - xsr[3 * j]), (T)(x1 - xsr[3 * j + 1]),
-                        (T)(x2 - xsr[3 * j + 2]), rs);
+                        (T)(x2 - xsr[3 * j + 2]), rs, ik & 1, j & 1);
         for (int m = 0; m < k; ++m) {
           T qv[9];
           const T* qm = pool + fp[m] + 9 * (int64_t)c + 9 * (int64_t)j;
@@ -259,6 +259,9 @@ extern "C" hh_status hh_aca_build_pivots(hh_ctx ctx, hh_tree tree, hh_part part,
   HH_API_BEGIN(ctx)
   HH_REQUIRE(out && tree && part && kern, HH_ERR_INVALID_ARG, "NULL argument");
   HH_REQUIRE(part->tree == tree, HH_ERR_INVALID_ARG, "partition was built on another tree");
+  check_kernel_tree(tree, kern);
+  HH_REQUIRE(kern->kind != KIND_RPY6 || prec == HH_FP64 || prec == HH_FP32, HH_ERR_INVALID_ARG,
+             "the 6N kernel runs in HH_FP64 and HH_FP32");
   *out = build_lowrank_pivots(ctx, tree, part, kern, prec, rank, fallback, piv_i, piv_j);
   HH_API_END(ctx)
 }

@@ -291,8 +291,8 @@ hh_status hh_short_create(hh_ctx ctx, hh_tree tree, const double* s2_params,
   HH_API_BEGIN(ctx)
   HH_REQUIRE(out && tree && s2_params && g3_params, HH_ERR_INVALID_ARG, "NULL argument");
   HH_REQUIRE(tree->ctx == ctx, HH_ERR_INVALID_ARG, "tree belongs to another context");
-  HH_REQUIRE(tree->n_sys == 1, HH_ERR_INVALID_ARG,
-             "the short-range terms take a single-system tree");
+  HH_REQUIRE(tree->n_sys == 1 && !tree->six, HH_ERR_INVALID_ARG,
+             "the short-range terms take a single-system tree of particles");
   HH_REQUIRE(r_cut > 0 && std::isfinite(r_cut), HH_ERR_INVALID_ARG, "r_cut must be > 0");
   for (int i = 0; i < MLP_NP; ++i)
     HH_REQUIRE(std::isfinite(s2_params[i]), HH_ERR_INVALID_ARG, "non-finite parameter");

@@ -421,18 +421,59 @@ __global__ __launch_bounds__(T256) void k_roots(const int4* __restrict__ nodes, 
 inline unsigned nblk(int64_t n, int t = T256) { return (unsigned)((n + t - 1) / t); }
 
 // Refit: new positions in the kept order (xs[s] = X[perm[s]]).
+// shift = 1 on a tree of 6N rows: row perm[s] belongs to particle perm[s] >> 1
 __global__ __launch_bounds__(T256) void k_refit_gather(const double* __restrict__ X, int64_t n,
                                                        const int32_t* __restrict__ perm,
-                                                       double* __restrict__ xs,
+                                                       int shift, double* __restrict__ xs,
                                                        int* __restrict__ bad) {
   int64_t s = (int64_t)blockIdx.x * T256 + threadIdx.x;
   if (s >= n) return;
-  const int64_t o = perm[s];
+  const int64_t o = perm[s] >> shift;
   const double x0 = X[3 * o], x1 = X[3 * o + 1], x2 = X[3 * o + 2];
   if (!isfinite(x0) || !isfinite(x1) || !isfinite(x2)) atomicOr(bad, 1);
   xs[3 * s] = x0;
   xs[3 * s + 1] = x1;
   xs[3 * s + 2] = x2;
+}
+
+// Rows of the 6N tree from the particle tree: sorted row s = 2p + r is row r
+// (0: translation, 1: rotation) of sorted particle p, input row 2 perm[p] + r.
+__global__ __launch_bounds__(T256) void k_six_rows(int64_t n2, const int32_t* __restrict__ perm1,
+                                                   const uint64_t* __restrict__ keys1,
+                                                   const double* __restrict__ xs1,
+                                                   const int32_t* __restrict__ leaf_of1,
+                                                   int32_t* __restrict__ perm,
+                                                   uint64_t* __restrict__ keys,
+                                                   double* __restrict__ xs,
+                                                   int32_t* __restrict__ leaf_of) {
+  int64_t s = (int64_t)blockIdx.x * T256 + threadIdx.x;
+  if (s >= n2) return;
+  const int64_t p = s >> 1;
+  perm[s] = 2 * perm1[p] + (int32_t)(s & 1);
+  keys[s] = keys1[p];
+  xs[3 * s] = xs1[3 * p];
+  xs[3 * s + 1] = xs1[3 * p + 1];
+  xs[3 * s + 2] = xs1[3 * p + 2];
+  leaf_of[s] = leaf_of1[p];
+}
+
+__global__ __launch_bounds__(T256) void k_six_nodes(int64_t m, int4* __restrict__ nodes) {
+  int64_t i = (int64_t)blockIdx.x * T256 + threadIdx.x;
+  if (i >= m) return;
+  int4 v = nodes[i];
+  v.x *= 2;
+  v.y *= 2;
+  nodes[i] = v;
+}
+
+// moves the storage of src into dst (both on the context stream)
+void take(DevBuf& dst, DevBuf& src) {
+  dst.release();
+  dst.p = src.p;
+  dst.bytes = src.bytes;
+  dst.s = src.s;
+  src.p = nullptr;
+  src.bytes = 0;
 }
 
 }  // namespace
@@ -582,6 +623,60 @@ hh_status hh_build_tree(hh_ctx ctx, const double* X, int64_t n, int32_t c_leaf, 
   HH_API_END(ctx)
 }
 
+hh_status hh_build_tree6(hh_ctx ctx, const double* X, int64_t n, int32_t c_leaf, hh_tree* out) {
+  if (out) *out = nullptr;
+  HH_API_BEGIN(ctx)
+  HH_REQUIRE(out && X, HH_ERR_INVALID_ARG, "NULL argument");
+  HH_REQUIRE(n >= 1 && n < (1ll << 30) - 1, HH_ERR_INVALID_ARG, "n must be in [1, 2^30-2]");
+  HH_REQUIRE(c_leaf >= 2 && c_leaf < (1 << 29), HH_ERR_INVALID_ARG,
+             "c_leaf must be in [2, 2^29)");
+  PhaseTimer timer(ctx, HH_PHASE_TREE);
+  hipStream_t st = ctx->stream;
+  hh_tree_s one;   // the particle tree
+  hh_tree_s* t = new hh_tree_s();
+  try {
+    build_tree_impl(ctx, &one, X, n, std::vector<int64_t>{0, n}, std::vector<int32_t>{c_leaf});
+    const int64_t n2 = 2 * n, m = one.n_nodes;
+    t->ctx = ctx;
+    t->six = true;
+    t->n = n2;
+    t->c_leaf = 2 * c_leaf;
+    t->n_nodes = m;
+    t->n_leaves = one.n_leaves;
+    t->n_sys = 1;
+    t->offs_host = {0, n2};
+    t->offs.alloc(st, 2 * sizeof(int64_t));
+    HIP_OK(hipMemcpyAsync(t->offs.p, t->offs_host.data(), 2 * sizeof(int64_t),
+                          hipMemcpyHostToDevice, st));
+    const int32_t cl2 = 2 * c_leaf;
+    t->cl.alloc(st, sizeof(int32_t));
+    HIP_OK(hipMemcpyAsync(t->cl.p, &cl2, sizeof(int32_t), hipMemcpyHostToDevice, st));
+    t->perm.alloc(st, n2 * sizeof(int32_t));
+    t->keys.alloc(st, n2 * sizeof(uint64_t));
+    t->xs.alloc(st, 3 * n2 * sizeof(double));
+    t->leaf_of.alloc(st, n2 * sizeof(int32_t));
+    hipLaunchKernelGGL(k_six_rows, dim3(nblk(n2)), dim3(T256), 0, st, n2, one.perm.as<int32_t>(),
+                       one.keys.as<uint64_t>(), one.xs.as<double>(), one.leaf_of.as<int32_t>(),
+                       t->perm.as<int32_t>(), t->keys.as<uint64_t>(), t->xs.as<double>(),
+                       t->leaf_of.as<int32_t>());
+    take(t->nodes, one.nodes);
+    hipLaunchKernelGGL(k_six_nodes, dim3(nblk(m)), dim3(T256), 0, st, m, t->nodes.as<int4>());
+    HIP_OK(hipGetLastError());
+    take(t->parent, one.parent);
+    take(t->bbox, one.bbox);
+    take(t->leaf_id, one.leaf_id);
+    take(t->leaves, one.leaves);
+    take(t->roots, one.roots);
+    ensure_units(ctx, t);
+    ctx_sync(ctx);   // the host values above stay valid until the copies ran
+  } catch (...) {
+    delete t;
+    throw;
+  }
+  *out = t;
+  HH_API_END(ctx)
+}
+
 static hh_status build_batch(hh_ctx ctx, const double* X, const int64_t* offsets, int32_t n_sys,
                              const int32_t* c_leafs, int32_t c_leaf, hh_tree* out) {
   if (out) *out = nullptr;
@@ -634,7 +729,7 @@ hh_status hh_tree_refit(hh_ctx ctx, hh_tree tree, const double* X) {
   int* bad = (int*)ctx->scratch_flag.p;
   HIP_OK(hipMemsetAsync(bad, 0, sizeof(int64_t), st));
   hipLaunchKernelGGL(k_refit_gather, dim3(nblk(n)), dim3(T256), 0, st, X, n,
-                     tree->perm.as<int32_t>(), tree->xs.as<double>(), bad);
+                     tree->perm.as<int32_t>(), tree->six ? 1 : 0, tree->xs.as<double>(), bad);
   hipLaunchKernelGGL(k_leaf_box, dim3(nblk(nl * 64)), dim3(T256), 0, st,
                      tree->leaves.as<int32_t>(), nl, tree->nodes.as<int4>(), tree->xs.as<double>(),
                      tree->leaf_of.as<int32_t>(), tree->bbox.as<double>());

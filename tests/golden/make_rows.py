@@ -4,7 +4,8 @@ For a workload (workloads.workload(name)) and k rows sampled uniformly
 without replacement (workloads.sample_rows(n, k, seed=3)), stores the exact
 dense product U_i = alpha_1 F_i + sum_{j != i} K(x_i - x_j) F_j of those rows
 (Eq. (2) restricted to the one-body and two-body terms), as computed by
-oracle.dense, in tests/golden/rows_<workload>.npz together with SHA-256
+oracle.dense (for the 6N kernel: the rows (U_i, w_i) of oracle.rotation's
+dense 6N product), in tests/golden/rows_<workload>.npz together with SHA-256
 digests of X and F, so a reader can check that it compares against the same
 inputs. For a workload of many independent systems, k / n_sys rows are
 sampled in each system (workloads.sample_rows(n_s, k / n_sys, seed=3)) and
@@ -31,6 +32,7 @@ sys.path.insert(0, ROOT)
 import workloads as wl  # noqa: E402
 from oracle import dense as OD  # noqa: E402
 from oracle import kernels as OK  # noqa: E402
+from oracle import rotation as OR  # noqa: E402
 
 _X = _F = _K = None
 
@@ -40,6 +42,8 @@ def digest(a) -> str:
 
 
 def oracle_kernel(cfg):
+    if cfg["kernel"] == "rpy6":
+        return "rpy6"
     if cfg["kernel"] == "rpy":
         return OK.Kernel("rpy")
     return OK.Kernel("mlp", OK.MLP(*wl.mlp_weights(1)), inp="direction")
@@ -58,6 +62,9 @@ def _init(X, F, kind):
 
 def _rows(task):
     a, b, rows = task   # particles [a, b) form the row's system; rows are local
+    if isinstance(_K, str):   # the 6N kernel
+        U, W = OR.u6(_X[a:b], _F[a:b, :3], _F[a:b, 3:], rows=rows)
+        return np.hstack([U, W])
     return OD.dense_u(_X[a:b], _F[a:b], _K, rows)
 
 

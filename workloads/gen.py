@@ -380,6 +380,10 @@ WORKLOADS = {
     "filaments_215k": dict(n=215040, geom="filaments", phi=None, seed=0, forces="gravity",
                            kernel="mlp", precision="bf16", c_leaf=128, eta=1.0, eps=0.02,
                            n_fil=5120, n_beads=21, bond=3.0, dt=0.002, k_t=20.0, k_b=50.0),
+    # the 6N product with rotations: forces and torques ~ N(0, I3) on 1M
+    # particles of the plain random suspension (F holds (F_i, T_i), [n][6])
+    "rotation_1m": dict(n=1000000, geom="cube", phi=0.20, seed=0, forces="normal+torques",
+                        kernel="rpy6", precision="fp32", c_leaf=64, eta=1.0, eps=1e-5),
     # 64 independent systems (batch_workload): n is the total, set when generated
     "batch64": dict(n=None, geom="batch", phi=None, seed=2, forces="normal",
                     kernel="mlp", precision="bf16", c_leaf=128, eta=1.0, eps=1e-4),
@@ -409,6 +413,9 @@ def workload(name: str, n: int | None = None):
         X = lattice_sphere(w["n"], w["phi"], seed=w["seed"])
     if w["forces"] == "normal":
         F = normal_forces(w["n"], seed=w["seed"])
+    elif w["forces"] == "normal+torques":
+        F = np.hstack([normal_forces(w["n"], seed=w["seed"]),
+                       normal_forces(w["n"], seed=w["seed"] + 1)])
     else:
         F = gravity_forces(w["n"], seed=w["seed"])
     return X, F, w
