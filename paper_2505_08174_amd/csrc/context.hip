@@ -8,6 +8,7 @@
 #include "api_guard.h"
 #include "devmath.h"
 #include "internal.h"
+#include "mlp_mfma.h"
 
 void DevBuf::release() {
   if (p) {
@@ -230,6 +231,45 @@ static std::vector<uint16_t> build_bf16_frags(const double* P0) {
   return fr;
 }
 
+// Fragment table of the FP32 MFMA MLP (layout in mlp_mfma.h): one float per
+// lane and K step. Layers 1-3 scaled by 2 log2(e) as for the BF16 table.
+static std::vector<float> build_f32_frags(const double* P0) {
+  std::vector<float> fr((size_t)F32_FRAGS * 64, 0.0f);
+  auto at = [&](int frag, int lane) -> float& { return fr[(size_t)frag * 64 + lane]; };
+  const double S = 2.0 / log(2.0);
+  const double* W1 = P0 + OFF_W1;
+  const double* b1 = P0 + OFF_B1;
+  // feature contracted by K slot h of step (mo, r)
+  auto feat = [](int mo, int r, int h) { return 32 * mo + 8 * (r / 4) + 4 * h + (r % 4); };
+  for (int mo = 0; mo < 2; ++mo)
+    for (int lane = 0; lane < 64; ++lane) {
+      const int m = 32 * mo + (lane & 31), h = lane >> 5;
+      at(F32_L1 + 2 * mo, lane) = (float)(S * W1[3 * m + h]);
+      at(F32_L1 + 2 * mo + 1, lane) = (float)(S * (h == 0 ? W1[3 * m + 2] : b1[m]));
+    }
+  auto hidden = [&](int base, const double* W, const double* b) {
+    for (int mp = 0; mp < 2; ++mp)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int m = 32 * mp + (lane & 31), h = lane >> 5;
+        for (int mo = 0; mo < 2; ++mo)
+          for (int r = 0; r < 16; ++r)
+            at(base + (mp * 2 + mo) * 16 + r, lane) = (float)(S * W[MLP_H * m + feat(mo, r, h)]);
+        at(base + 64 + mp, lane) = h == 0 ? (float)(S * b[m]) : 0.0f;
+      }
+  };
+  hidden(F32_L2, P0 + OFF_W2, P0 + OFF_B2);
+  hidden(F32_L3, P0 + OFF_W3, P0 + OFF_B3);
+  for (int lane = 0; lane < 64; ++lane) {
+    const int m = lane & 31, h = lane >> 5;
+    if (m >= 9) continue;
+    for (int mo = 0; mo < 2; ++mo)
+      for (int r = 0; r < 16; ++r)
+        at(F32_L4 + mo * 16 + r, lane) = (float)P0[OFF_W4 + MLP_H * m + feat(mo, r, h)];
+    if (h == 0) at(F32_L4 + 32, lane) = (float)P0[OFF_B4 + m];
+  }
+  return fr;
+}
+
 extern "C" {
 
 hh_status hh_ctx_create(int device, void* stream, hh_ctx* out) {
@@ -400,6 +440,10 @@ hh_status hh_kernel_create_mlp(hh_ctx ctx, const double* params, int input_mode,
     std::vector<uint16_t> fr = build_bf16_frags(params);
     k->pbf.alloc(ctx->stream, fr.size() * sizeof(uint16_t));
     HIP_OK(hipMemcpyAsync(k->pbf.p, fr.data(), fr.size() * sizeof(uint16_t),
+                          hipMemcpyHostToDevice, ctx->stream));
+    std::vector<float> f32 = build_f32_frags(params);
+    k->pf32.alloc(ctx->stream, f32.size() * sizeof(float));
+    HIP_OK(hipMemcpyAsync(k->pf32.p, f32.data(), f32.size() * sizeof(float),
                           hipMemcpyHostToDevice, ctx->stream));
     k->p64.alloc(ctx->stream, MLP_NP * sizeof(double));
     k->p32.alloc(ctx->stream, MLP_NP * sizeof(float));

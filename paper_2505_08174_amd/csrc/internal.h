@@ -108,6 +108,7 @@ struct hh_kernel_s {
   DevBuf p64;                       // MLP params FP64, packed
   DevBuf p32;                       // MLP params FP32, packed
   DevBuf pbf;                       // MLP params for the BF16 MFMA path
+  DevBuf pf32;                      // MLP params for the FP32 MFMA path (fragment table)
 };
 
 // Offsets of the packed MLP parameter vector.
@@ -253,6 +254,7 @@ void launch_near(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, int prec, const 
                  void* Unear);
 void launch_near_bf16(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void* Fs, void* Un,
                       bool split);
+void launch_near_f32(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void* Fs, void* Un);
 void ensure_units(hh_ctx ctx, hh_tree t);
 void launch_near_neg(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, int prec, const void* Vs,
                      void* out);

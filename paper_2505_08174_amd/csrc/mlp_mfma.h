@@ -200,3 +200,98 @@ __device__ __forceinline__ void stage_frags(bf16x8* __restrict__ lds, const uint
   uint4* d = reinterpret_cast<uint4*>(lds);
   for (int i = threadIdx.x; i < FR_TOTAL; i += nthreads) d[i] = g[i];
 }
+
+// ------------------------------------------------------------ FP32 MFMA tile
+//
+// The same MLP for one wave-tile of 32 pairs on FP32 MFMA
+// (v_mfma_f32_32x32x2_f32: FP32 operands and accumulation, the plain FP32
+// form). Lane l works on pair l % 32 and supplies K slot h = l / 32 of every
+// product. A result register r of lane l holds row 8 (r / 4) + 4 h + r % 4
+// of its M tile; K step (mo, r) of the next layer contracts the two features
+// 32 mo + 8 (r / 4) + r % 4 + 4 h, h = 0, 1, which are exactly what the two
+// halves of the wave hold in register r, so a layer's tanh output is the next
+// layer's B operand with no data motion (the weights are stored permuted to
+// that order, one float per lane and step). Layer 1 contracts (v0, v1) and
+// (v2, 1), the 1 carrying the bias; layers 2-4 take their bias through one
+// extra step whose B operand is (1, 0). Layers 1-3 are stored scaled by
+// 2 log2(e) (see tanh_scaled).
+#define F32_L1 0                               // [mo 2][step 2]
+#define F32_L2 (F32_L1 + 4)                    // [mo' 2][mo 2][r 16], bias [mo' 2]
+#define F32_L3 (F32_L2 + 66)
+#define F32_L4 (F32_L3 + 66)                   // [mo 2][r 16], bias
+#define F32_FRAGS (F32_L4 + 33)
+#define F32_BYTES (F32_FRAGS * 64 * 4)
+
+__device__ __forceinline__ f32x16 mfma_f32(float a, float b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+// One hidden layer (64 -> 64, then tanh) from h[2][16] into g[2][16]; the two
+// output M tiles are two independent MFMA chains.
+__device__ __forceinline__ void hidden_f32(const float* __restrict__ fr, int base, int lane,
+                                           float bone, const float (&h)[2][16],
+                                           float (&g)[2][16]) {
+  f32x16 a0 = mfma_f32(fr[(base + 64) * 64 + lane], bone, f32x16{});
+  f32x16 a1 = mfma_f32(fr[(base + 65) * 64 + lane], bone, f32x16{});
+#pragma unroll
+  for (int mo = 0; mo < 2; ++mo)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      a0 = mfma_f32(fr[(base + (0 * 2 + mo) * 16 + r) * 64 + lane], h[mo][r], a0);
+      a1 = mfma_f32(fr[(base + (1 * 2 + mo) * 16 + r) * 64 + lane], h[mo][r], a1);
+    }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    g[0][r] = tanh_scaled(a0[r]);
+    g[1][r] = tanh_scaled(a1[r]);
+  }
+}
+
+// Raw outputs o[0..8] of the MLP at input (v0, v1, v2) for this lane's pair.
+// Must be called by all 64 lanes with lanes l and l + 32 holding the same
+// input. fr: the FP32 fragment table (F32_FRAGS x 64 floats).
+__device__ __forceinline__ void mlp_tile_f32(const float* __restrict__ fr, float v0, float v1,
+                                             float v2, float o[9]) {
+  __asm__ volatile("" ::: "memory");
+  const int lane = threadIdx.x & 63;
+  const bool h1 = lane >= 32;
+  const float bone = h1 ? 0.0f : 1.0f;
+  float h[2][16], g[2][16];
+  {
+    const float b0 = h1 ? v1 : v0, b1 = h1 ? 1.0f : v2;
+#pragma unroll
+    for (int mo = 0; mo < 2; ++mo) {
+      f32x16 a = mfma_f32(fr[(F32_L1 + 2 * mo) * 64 + lane], b0, f32x16{});
+      a = mfma_f32(fr[(F32_L1 + 2 * mo + 1) * 64 + lane], b1, a);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) h[mo][r] = tanh_scaled(a[r]);
+    }
+  }
+  hidden_f32(fr, F32_L2, lane, bone, h, g);
+  hidden_f32(fr, F32_L3, lane, bone, g, h);
+  // layer 4: two chains (features of M tile 0 and 1), summed at the end
+  f32x16 c0 = mfma_f32(fr[(F32_L4 + 32) * 64 + lane], bone, f32x16{});
+  f32x16 c1 = f32x16{};
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    c0 = mfma_f32(fr[(F32_L4 + r) * 64 + lane], h[0][r], c0);
+    c1 = mfma_f32(fr[(F32_L4 + 16 + r) * 64 + lane], h[1][r], c1);
+  }
+  // rows 0-3 and 8 live in lanes 0-31 (registers 0-3, 4); rows 4-7 in 32-63
+  float c[5];
+#pragma unroll
+  for (int e = 0; e < 5; ++e) c[e] = c0[e] + c1[e];
+  const float t0 = __shfl_xor(c[0], 32, 64), t1 = __shfl_xor(c[1], 32, 64);
+  const float t2 = __shfl_xor(c[2], 32, 64), t3 = __shfl_xor(c[3], 32, 64);
+  const float t4 = __shfl_xor(c[4], 32, 64);
+  o[0] = h1 ? t0 : c[0]; o[1] = h1 ? t1 : c[1]; o[2] = h1 ? t2 : c[2];
+  o[3] = h1 ? t3 : c[3]; o[4] = h1 ? c[0] : t0; o[5] = h1 ? c[1] : t1;
+  o[6] = h1 ? c[2] : t2; o[7] = h1 ? c[3] : t3; o[8] = h1 ? t4 : c[4];
+}
+
+// Stage the FP32 fragment table (global -> LDS) by the whole workgroup.
+__device__ __forceinline__ void stage_frags_f32(float* __restrict__ lds,
+                                                const float4* __restrict__ g, int nthreads) {
+  float4* d = reinterpret_cast<float4*>(lds);
+  for (int i = threadIdx.x; i < F32_FRAGS * 16; i += nthreads) d[i] = g[i];
+}

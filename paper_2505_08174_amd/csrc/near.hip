@@ -125,6 +125,8 @@ void launch_near(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, int prec, const 
                  void* Un) {
   if (prec == HH_FP64)
     launch_near_t<double>(ctx, t, p, k, Fs, Un);
+  else if (prec == HH_FP32 && k->kind == KIND_MLP)
+    launch_near_f32(ctx, t, p, k, Fs, Un);
   else if (prec == HH_FP32 || k->kind != KIND_MLP)
     launch_near_t<float>(ctx, t, p, k, Fs, Un);
   else

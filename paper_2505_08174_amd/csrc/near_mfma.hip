@@ -118,6 +118,68 @@ __global__ __launch_bounds__(NB_T) void k_near_bf16(NearB a) {
   }
 }
 
+// The plain FP32 form on FP32 MFMA: the same work units and walk, one FP32
+// tile per source. F and U are FP32; each lane sums its target's terms in
+// FP64 and rounds once.
+struct NearF {
+  const float4* frags;
+  const int4* nodes;
+  const int32_t* leaves;
+  const int32_t* near_ptr;
+  const int2* H;
+  const int2* units;
+  int64_t n_units;
+  const double* xs;
+  const float* Fs;
+  float* Un;
+  int input_mode;
+};
+
+__global__ __launch_bounds__(NB_T) void k_near_f32(NearF a) {
+  __shared__ float fr[F32_FRAGS * 64];
+  stage_frags_f32(fr, a.frags, NB_T);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t unit = (int64_t)blockIdx.x * (NB_T / 64) + w;
+  if (unit >= a.n_units) return;
+  const int2 un = a.units[unit];
+  const int4 nt = a.nodes[a.leaves[un.x]];
+  const int i = nt.x + 32 * un.y + (lane & 31);
+  const bool act = i < nt.y;
+  const int ii = act ? i : nt.x;
+  const double xi0 = a.xs[3 * (int64_t)ii], xi1 = a.xs[3 * (int64_t)ii + 1],
+               xi2 = a.xs[3 * (int64_t)ii + 2];
+  const bool dir = a.input_mode == HH_MLP_INPUT_DIRECTION;
+  const float c16 = (float)(1.0 / (16.0 * HH_PI));
+  double u0 = 0, u1 = 0, u2 = 0;
+  const int p0 = a.near_ptr[un.x], p1 = a.near_ptr[un.x + 1];
+  for (int p = p0; p < p1; ++p) {
+    const int4 ns = a.nodes[a.H[p].y];
+    for (int j = ns.x; j < ns.y; ++j) {
+      float rx = (float)(xi0 - a.xs[3 * (int64_t)j]);
+      float ry = (float)(xi1 - a.xs[3 * (int64_t)j + 1]);
+      float rz = (float)(xi2 - a.xs[3 * (int64_t)j + 2]);
+      const bool skip = (j == ii) || !act;
+      if (j == ii) { rx = 1.0f; ry = 0.0f; rz = 0.0f; }
+      const float rs = hh_rsqrt(rx * rx + ry * ry + rz * rz);
+      const float sv = dir ? rs : 1.0f;
+      float q[9];
+      mlp_tile_f32(fr, rx * sv, ry * sv, rz * sv, q);
+      const float sc = skip ? 0.0f : rs * c16;
+      const float f0 = a.Fs[3 * (int64_t)j], f1 = a.Fs[3 * (int64_t)j + 1],
+                  f2 = a.Fs[3 * (int64_t)j + 2];
+      u0 += (double)(sc * (2.0f * q[0] * f0 + (q[1] + q[3]) * f1 + (q[2] + q[6]) * f2));
+      u1 += (double)(sc * ((q[3] + q[1]) * f0 + 2.0f * q[4] * f1 + (q[5] + q[7]) * f2));
+      u2 += (double)(sc * ((q[6] + q[2]) * f0 + (q[7] + q[5]) * f1 + 2.0f * q[8] * f2));
+    }
+  }
+  if (act && lane < 32) {
+    a.Un[3 * (int64_t)i] = (float)u0;
+    a.Un[3 * (int64_t)i + 1] = (float)u1;
+    a.Un[3 * (int64_t)i + 2] = (float)u2;
+  }
+}
+
 }  // namespace
 
 // Work units (leaf rank, chunk of 32 targets), built once per tree.
@@ -161,5 +223,25 @@ void launch_near_bf16(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void*
     hipLaunchKernelGGL(k_near_bf16<true>, dim3(grid), dim3(NB_T), 0, ctx->stream, a);
   else
     hipLaunchKernelGGL(k_near_bf16<false>, dim3(grid), dim3(NB_T), 0, ctx->stream, a);
+  HIP_OK(hipGetLastError());
+}
+
+void launch_near_f32(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void* Fs, void* Un) {
+  HH_REQUIRE(k->kind == KIND_MLP, HH_ERR_INVALID_ARG, "the FP32 MFMA tile needs the MLP kernel");
+  ensure_units(ctx, t);
+  NearF a;
+  a.frags = k->pf32.as<float4>();
+  a.nodes = t->nodes.as<int4>();
+  a.leaves = t->leaves.as<int32_t>();
+  a.near_ptr = p->near_ptr.as<int32_t>();
+  a.H = p->H.as<int2>();
+  a.units = t->units.as<int2>();
+  a.n_units = t->n_units;
+  a.xs = t->xs.as<double>();
+  a.Fs = (const float*)Fs;
+  a.Un = (float*)Un;
+  a.input_mode = k->input_mode;
+  unsigned grid = (unsigned)((t->n_units + 3) / 4);
+  hipLaunchKernelGGL(k_near_f32, dim3(grid), dim3(NB_T), 0, ctx->stream, a);
   HIP_OK(hipGetLastError());
 }

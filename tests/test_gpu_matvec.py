@@ -50,6 +50,25 @@ def test_dense_mode_fp64(kind):
     assert _rel(U, Ud) < 1e-10 and _row(U, Ud) < 1e-10
 
 
+@pytest.mark.parametrize("inp", ["direction", "displacement"])
+def test_dense_mode_fp32_mlp(inp):
+    """The plain FP32 form's near field (the MLP on FP32 MFMA tiles, FP32
+    operands and accumulation) over every pair. Per entry the FP32 rounding
+    of four layers of 64-term sums is a few 1e-7; the sum over sources adds at
+    most the ratio sum|K F| / |sum K F| (below ~10 for these forces), so the
+    bound is 1e-5 on the 2-norm and on the worst particle."""
+    from gpu_common import ctx, dev, kernels, say
+    n = 900
+    X = wl.rsa_cube(n, 0.1, seed=2)
+    F = wl.normal_forces(n, seed=2)
+    ko, kg = kernels("mlp", inp)
+    Ud = OD.dense_u(X, F, ko)
+    hm = hh.HMatrix(ctx(), dev(X), kg, c_leaf=64, prec="fp32", dense_mode=True)
+    U = (hm @ dev(F, torch.float32)).double().cpu().numpy()
+    say("dense mode fp32 mlp", inp, "rel", _rel(U, Ud), "worst row", _row(U, Ud))
+    assert _rel(U, Ud) < 1e-5 and _row(U, Ud) < 1e-5
+
+
 def test_hmatvec_fp64_rpy_plain_small():
     from gpu_common import ctx, dev, kernels, say
     say("plain small fp64 rpy")
