@@ -12,7 +12,8 @@
 //  back-propagated the same way.
 // Accumulation: dX of a target row in registers, of a source row with FP64
 // atomics; dtheta per workgroup in LDS (FP64 in every form), then summed over
-// workgroups in a fixed order in FP64.
+// workgroups in a fixed order in FP64. The FP32 form back-propagates the near
+// pairs and the ACA samples on FP32 MFMA tiles instead (backward_mfma.hip).
 #include "api_guard.h"
 #include "devmath.h"
 #include "internal.h"
@@ -24,8 +25,9 @@ namespace {
 
 constexpr int TB = 256;
 inline unsigned nblk(int64_t n) { return (unsigned)((n + TB - 1) / TB); }
-// cotangent-pool elements per chunk of blocks (1 GiB in FP32)
-constexpr int64_t GPOOL_CHUNK = 256ll << 20;
+// cotangent-pool elements per chunk of blocks (8 GiB in FP32): few chunks, so
+// that the back-propagation of the samples runs in few launches
+constexpr int64_t GPOOL_CHUNK = 2048ll << 20;
 
 // dtheta: every wave sums its 64 lanes' contributions to a parameter with DPP
 // (all lanes active, a fixed order), and one lane per wave adds the total to
@@ -671,8 +673,12 @@ void backward_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kernel k, co
     dXs.alloc(st, 3 * n * sizeof(double));
     HIP_OK(hipMemsetAsync(dXs.p, 0, 3 * n * sizeof(double), st));
   }
-  const int gnear = (int)t->n_leaves;
-  const int gfar = (int)std::min<int64_t>(std::max<int64_t>(nG, 1), 2048);
+  // FP32: near and sampled pairs on the FP32 MFMA tile (persistent waves, one
+  // dtheta slot per wave); FP64: the VALU kernels (one slot per workgroup)
+  constexpr bool mf = sizeof(T) == 4;
+  const int gnear = mf ? (int)vjp_f32_waves(ctx) : (int)t->n_leaves;
+  const int gfar = mf ? (int)vjp_f32_waves(ctx)
+                      : (int)std::min<int64_t>(std::max<int64_t>(nG, 1), 2048);
   const int nparts = gnear + gfar + gfb;   // dtheta partial slots: near, far, fallback
   if (mlp) {
     part.alloc(st, (int64_t)nparts * MLP_NP * sizeof(double));
@@ -688,7 +694,10 @@ void backward_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kernel k, co
                        lr->piv.as<int32_t>(), lr->fptr.as<int64_t>(), goff.as<int64_t>(),
                        lr->pool.as<T>(), gpool.as<T>(), Fs.as<T>(), ws.as<T>(),
                        farT.as<double>());
-    if (mlp)
+    if (mlp && mf)
+      launch_far_vjp_f32(ctx, t, p, lr, k, b0, b1, goff.as<int64_t>(), gpool.as<float>(),
+                         dXs.as<double>(), part.as<double>() + (int64_t)gnear * MLP_NP);
+    else if (mlp)
       hipLaunchKernelGGL((k_far_vjp<T>), dim3(gfar), dim3(TB), 0, st, p->G.as<int2>(), b0, b1,
                          t->nodes.as<int4>(), lr->rank.as<int32_t>(), lr->flag.as<int32_t>(),
                          lr->piv.as<int32_t>(), goff.as<int64_t>(), gpool.as<T>(),
@@ -719,10 +728,14 @@ void backward_t(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kernel k, co
                        (T*)dF);
   }
   if (mlp) {
-    hipLaunchKernelGGL((k_near_vjp<T>), dim3(gnear), dim3(TB), 0, st, t->nodes.as<int4>(),
-                       t->leaves.as<int32_t>(), p->near_ptr.as<int32_t>(), p->H.as<int2>(),
-                       t->xs.as<double>(), Fs.as<T>(), ws.as<T>(), wgt, k->input_mode,
-                       dXs.as<double>(), part.as<double>());
+    if constexpr (mf)
+      launch_near_vjp_f32(ctx, t, p, k, Fs.as<float>(), ws.as<float>(), dXs.as<double>(),
+                          part.as<double>());
+    else
+      hipLaunchKernelGGL((k_near_vjp<T>), dim3(gnear), dim3(TB), 0, st, t->nodes.as<int4>(),
+                         t->leaves.as<int32_t>(), p->near_ptr.as<int32_t>(), p->H.as<int2>(),
+                         t->xs.as<double>(), Fs.as<T>(), ws.as<T>(), wgt, k->input_mode,
+                         dXs.as<double>(), part.as<double>());
     HIP_OK(hipGetLastError());
     if (dX)
       hipLaunchKernelGGL(k_scatter_dX, dim3(nblk(n)), dim3(TB), 0, st, dXs.as<double>(),

@@ -270,6 +270,33 @@ static std::vector<float> build_f32_frags(const double* P0) {
   return fr;
 }
 
+// Transposed weights of the FP32 MFMA backward (layout in backward_mfma.hip),
+// unscaled: [W4^T: mo' 2][s 5], [W3^T: mo' 2][mo 2][r 16], [W2^T: same],
+// then W1 by feature [d 3][64].
+static std::vector<float> build_f32_bwd(const double* P0) {
+  const int B4 = 0, B3 = 10, B2 = 74, B1 = 138, NF = 141;
+  std::vector<float> fr((size_t)NF * 64, 0.0f);
+  auto at = [&](int frag, int lane) -> float& { return fr[(size_t)frag * 64 + lane]; };
+  auto feat = [](int mo, int r, int h) { return 32 * mo + 8 * (r / 4) + 4 * h + (r % 4); };
+  for (int mp = 0; mp < 2; ++mp)
+    for (int lane = 0; lane < 64; ++lane) {
+      const int col = 32 * mp + (lane & 31), h = lane >> 5;
+      for (int s = 0; s < 5; ++s) {
+        const int m = 2 * s + h;
+        if (m < 9) at(B4 + mp * 5 + s, lane) = (float)P0[OFF_W4 + MLP_H * m + col];
+      }
+      for (int mo = 0; mo < 2; ++mo)
+        for (int r = 0; r < 16; ++r) {
+          const int f = feat(mo, r, h);
+          at(B3 + (mp * 2 + mo) * 16 + r, lane) = (float)P0[OFF_W3 + MLP_H * f + col];
+          at(B2 + (mp * 2 + mo) * 16 + r, lane) = (float)P0[OFF_W2 + MLP_H * f + col];
+        }
+    }
+  for (int d = 0; d < 3; ++d)
+    for (int f = 0; f < 64; ++f) at(B1 + d, f) = (float)P0[OFF_W1 + 3 * f + d];
+  return fr;
+}
+
 extern "C" {
 
 hh_status hh_ctx_create(int device, void* stream, hh_ctx* out) {
@@ -444,6 +471,10 @@ hh_status hh_kernel_create_mlp(hh_ctx ctx, const double* params, int input_mode,
     std::vector<float> f32 = build_f32_frags(params);
     k->pf32.alloc(ctx->stream, f32.size() * sizeof(float));
     HIP_OK(hipMemcpyAsync(k->pf32.p, f32.data(), f32.size() * sizeof(float),
+                          hipMemcpyHostToDevice, ctx->stream));
+    std::vector<float> f32t = build_f32_bwd(params);
+    k->pf32t.alloc(ctx->stream, f32t.size() * sizeof(float));
+    HIP_OK(hipMemcpyAsync(k->pf32t.p, f32t.data(), f32t.size() * sizeof(float),
                           hipMemcpyHostToDevice, ctx->stream));
     k->p64.alloc(ctx->stream, MLP_NP * sizeof(double));
     k->p32.alloc(ctx->stream, MLP_NP * sizeof(float));

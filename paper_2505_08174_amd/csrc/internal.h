@@ -109,6 +109,7 @@ struct hh_kernel_s {
   DevBuf p32;                       // MLP params FP32, packed
   DevBuf pbf;                       // MLP params for the BF16 MFMA path
   DevBuf pf32;                      // MLP params for the FP32 MFMA path (fragment table)
+  DevBuf pf32t;                     // transposed weights for the FP32 MFMA backward
 };
 
 // Offsets of the packed MLP parameter vector.
@@ -254,7 +255,17 @@ void launch_near(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, int prec, const 
                  void* Unear);
 void launch_near_bf16(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void* Fs, void* Un,
                       bool split);
-void launch_near_f32(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void* Fs, void* Un);
+// sgn = -1: the transposed product sum_j K(x_j - x_i) v_j
+void launch_near_f32(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void* Fs, void* Un,
+                     float sgn = 1.0f);
+// FP32 MFMA back-propagation of near pairs and of the ACA samples
+// (backward_mfma.hip); slots: vjp_f32_waves(ctx) x MLP_NP doubles each.
+int64_t vjp_f32_waves(hh_ctx ctx);
+void launch_near_vjp_f32(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const float* Fs,
+                         const float* ws, double* dXs, double* slots);
+void launch_far_vjp_f32(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, hh_kernel k,
+                        int64_t b0, int64_t b1, const int64_t* goff, const float* gpool,
+                        double* dXs, double* slots);
 void ensure_units(hh_ctx ctx, hh_tree t);
 void launch_near_neg(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, int prec, const void* Vs,
                      void* out);

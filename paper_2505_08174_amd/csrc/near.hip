@@ -117,6 +117,8 @@ void launch_near_neg(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, int prec, co
                      void* out) {
   if (prec == HH_FP64)
     launch_near_t<double>(ctx, t, p, k, Vs, out, -1.0);
+  else if (k->kind == KIND_MLP)
+    launch_near_f32(ctx, t, p, k, Vs, out, -1.0f);
   else
     launch_near_t<float>(ctx, t, p, k, Vs, out, -1.0);
 }

@@ -133,6 +133,7 @@ struct NearF {
   const float* Fs;
   float* Un;
   int input_mode;
+  float sgn;   // +1: K(x_i - x_j); -1: K(x_j - x_i) (the transposed product)
 };
 
 __global__ __launch_bounds__(NB_T) void k_near_f32(NearF a) {
@@ -156,9 +157,9 @@ __global__ __launch_bounds__(NB_T) void k_near_f32(NearF a) {
   for (int p = p0; p < p1; ++p) {
     const int4 ns = a.nodes[a.H[p].y];
     for (int j = ns.x; j < ns.y; ++j) {
-      float rx = (float)(xi0 - a.xs[3 * (int64_t)j]);
-      float ry = (float)(xi1 - a.xs[3 * (int64_t)j + 1]);
-      float rz = (float)(xi2 - a.xs[3 * (int64_t)j + 2]);
+      float rx = a.sgn * (float)(xi0 - a.xs[3 * (int64_t)j]);
+      float ry = a.sgn * (float)(xi1 - a.xs[3 * (int64_t)j + 1]);
+      float rz = a.sgn * (float)(xi2 - a.xs[3 * (int64_t)j + 2]);
       const bool skip = (j == ii) || !act;
       if (j == ii) { rx = 1.0f; ry = 0.0f; rz = 0.0f; }
       const float rs = hh_rsqrt(rx * rx + ry * ry + rz * rz);
@@ -226,7 +227,8 @@ void launch_near_bf16(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void*
   HIP_OK(hipGetLastError());
 }
 
-void launch_near_f32(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void* Fs, void* Un) {
+void launch_near_f32(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void* Fs, void* Un,
+                     float sgn) {
   HH_REQUIRE(k->kind == KIND_MLP, HH_ERR_INVALID_ARG, "the FP32 MFMA tile needs the MLP kernel");
   ensure_units(ctx, t);
   NearF a;
@@ -241,6 +243,7 @@ void launch_near_f32(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void* 
   a.Fs = (const float*)Fs;
   a.Un = (float*)Un;
   a.input_mode = k->input_mode;
+  a.sgn = sgn;
   unsigned grid = (unsigned)((t->n_units + 3) / 4);
   hipLaunchKernelGGL(k_near_f32, dim3(grid), dim3(NB_T), 0, ctx->stream, a);
   HIP_OK(hipGetLastError());
