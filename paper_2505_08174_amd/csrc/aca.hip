@@ -82,7 +82,8 @@ struct AcaArgs {
   const T* Fs;       // sorted forces
   double* ublk;      // per-block output rows [c][3], at uoff[pos] - uoff[b0]
   const int64_t* uoff;   // prefix sums of c over the work order (streamed mode)
-  const uint4* frags;   // BF16 MFMA weight fragments (MF kernels)
+  const uint4* frags;   // BF16 MFMA weight fragments (BF16 sampling)
+  const float4* frags32;   // FP32 MFMA weight fragments (FP32 sampling)
   int det_pivot;        // pivot magnitude |det| (else squared Frobenius norm)
   double* gram;         // Gram history A (gram_half doubles) and cross-wave
   int64_t gram_stride;  // partials, gram_stride doubles per worker
@@ -96,11 +97,20 @@ __device__ __forceinline__ NT det3(const T* K) {
               (NT)K[2] * ((NT)K[3] * (NT)K[7] - (NT)K[4] * (NT)K[6]));
 }
 
+// MFMA sampling of the kernel MLP: MFK = 1 BF16 tiles (hi + lo activations),
+// MFK = 2 FP32 tiles; fr is the matching fragment table in LDS.
+enum { MF_NONE = 0, MF_BF16 = 1, MF_F32 = 2 };
+
 // K(x_i - y_j) from NT independent MFMA MLP tiles: symmetrised 3x3 entries
-// of this lane's pair of each tile (accurate tiles: hi + lo activations).
-template <int NT>
-__device__ __forceinline__ void mfma_entries(const bf16x8* fr, int mode, const double (&d)[NT][3],
+// of this lane's pair of each tile.
+template <int NT, int MFK>
+__device__ __forceinline__ void mfma_entries(const void* fr, int mode, const double (&d)[NT][3],
                                              float (&K)[NT][9]) {
+  if constexpr (MFK == MF_F32) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) entry_f32tile((const float*)fr, mode, d[t][0], d[t][1], d[t][2], K[t]);
+    return;
+  }
   float v[NT][3], rs[NT], o[NT][9];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -111,7 +121,7 @@ __device__ __forceinline__ void mfma_entries(const bf16x8* fr, int mode, const d
     v[t][1] = ry * sc;
     v[t][2] = rz * sc;
   }
-  mlp_tiles_bf16<true, NT>(fr, v, o);
+  mlp_tiles_bf16<true, NT>((const bf16x8*)fr, v, o);
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const float s = rs[t] * (float)(1.0 / (16.0 * HH_PI));
@@ -121,11 +131,12 @@ __device__ __forceinline__ void mfma_entries(const bf16x8* fr, int mode, const d
   }
 }
 
-__device__ __forceinline__ void mfma_entry(const bf16x8* fr, int mode, double dx, double dy,
+template <int MFK>
+__device__ __forceinline__ void mfma_entry(const void* fr, int mode, double dx, double dy,
                                            double dz, float K[9]) {
   const double d[1][3] = {{dx, dy, dz}};
   float k1[1][9];
-  mfma_entries<1>(fr, mode, d, k1);
+  mfma_entries<1, MFK>(fr, mode, d, k1);
 #pragma unroll
   for (int e = 0; e < 9; ++e) K[e] = k1[0][e];
 }
@@ -260,8 +271,8 @@ __device__ __forceinline__ void team_sync() {
 // Raw samples K(sgn (p_i - y)) for rows i in [0, n) of `pts`, written to
 // slot[9 i ..]: 32-row MFMA tiles, lanes l and l + 32 share a row, the tiles
 // spread over the TW waves of the team.
-template <int NT>
-__device__ __forceinline__ void sample_tiles(const bf16x8* fr, int mode, const double* pts, int n,
+template <int NT, int MFK>
+__device__ __forceinline__ void sample_tiles(const void* fr, int mode, const double* pts, int n,
                                              double y0, double y1, double y2, double sgn,
                                              float* slot, int t0, int step) {
   const int lane = threadIdx.x & 63;
@@ -278,7 +289,7 @@ __device__ __forceinline__ void sample_tiles(const bf16x8* fr, int mode, const d
     d[t][2] = sgn * (pts[3 * ii + 2] - y2);
   }
   float K[NT][9];
-  mfma_entries<NT>(fr, mode, d, K);
+  mfma_entries<NT, MFK>(fr, mode, d, K);
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int i = row[t];
@@ -294,8 +305,8 @@ __device__ __forceinline__ void sample_tiles(const bf16x8* fr, int mode, const d
   }
 }
 
-template <int TW>
-__device__ __forceinline__ void sample_mfma(const bf16x8* fr, int mode, const double* pts, int n,
+template <int TW, int MFK>
+__device__ __forceinline__ void sample_mfma(const void* fr, int mode, const double* pts, int n,
                                             double y0, double y1, double y2, double sgn,
                                             float* slot, int wit) {
   // this wave's tiles t0, t0 + 32 TW, ... in pairs (two independent MFMA chains)
@@ -303,8 +314,8 @@ __device__ __forceinline__ void sample_mfma(const bf16x8* fr, int mode, const do
   int t0 = 32 * wit;
 #pragma unroll 1
   for (; t0 + step < n; t0 += 2 * step)
-    sample_tiles<2>(fr, mode, pts, n, y0, y1, y2, sgn, slot, t0, step);
-  if (t0 < n) sample_tiles<1>(fr, mode, pts, n, y0, y1, y2, sgn, slot, t0, step);
+    sample_tiles<2, MFK>(fr, mode, pts, n, y0, y1, y2, sgn, slot, t0, step);
+  if (t0 < n) sample_tiles<1, MFK>(fr, mode, pts, n, y0, y1, y2, sgn, slot, t0, step);
 }
 
 // Combines the per-wave results of a pass over the team: sums v[0..NV) in
@@ -378,8 +389,8 @@ __device__ __forceinline__ void team_combine(TeamRed* tr, double* gx, int wit, i
 // computes the per-step scalars itself from the same combined values, so all
 // decisions are uniform over the team. Fused apply: u(i) += c_{k-1}(i) t_{k-1}
 // rides on the next column pass (or a final pass).
-template <class T, int KIND, bool MF, int TW>
-__device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, const bf16x8* fr,
+template <class T, int KIND, int MF, int TW>
+__device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, const void* fr,
                                            TeamSh<T>& sh, TeamRed* tr, int wit, int64_t slot,
                                            int* counter, int64_t r0, int64_t r1, T* fbase,
                                            int64_t fcap) {
@@ -451,7 +462,7 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
       T* Ck = fb + offv;
       T* Qk = Ck + 9 * (int64_t)c;
       const double yj0 = xsr[3 * j], yj1 = xsr[3 * j + 1], yj2 = xsr[3 * j + 2];
-      if (MF) sample_mfma<TW>(fr, a.kp.input_mode, xt, c, yj0, yj1, yj2, 1.0, (float*)Ck, wit);
+      if (MF) sample_mfma<TW, MF>(fr, a.kp.input_mode, xt, c, yj0, yj1, yj2, 1.0, (float*)Ck, wit);
       team_sync<TW>();
       // ---- column pass: residual, Ghat, pivot search, sum a^T a
       NT best = -1, bestf = -1, graw = 0;
@@ -655,7 +666,7 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
         sh.qc[t] = fb[sh.off[m] + 9 * (int64_t)ik + e];
       }
       const double xi0 = xt[3 * ik], xi1 = xt[3 * ik + 1], xi2 = xt[3 * ik + 2];
-      if (MF) sample_mfma<TW>(fr, a.kp.input_mode, xsr, q, xi0, xi1, xi2, -1.0, (float*)Qk, wit);
+      if (MF) sample_mfma<TW, MF>(fr, a.kp.input_mode, xsr, q, xi0, xi1, xi2, -1.0, (float*)Qk, wit);
       team_sync<TW>();
       // ---- row pass: residual, Bhat, next column pivot, sum q_k q_k^T, t_k
       best = -1;
@@ -804,7 +815,7 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
 #pragma unroll 1
         for (int jj = 0; jj < q; ++jj) {
           float K[9];
-          mfma_entry(fr, a.kp.input_mode, x0 - xsr[3 * jj], x1 - xsr[3 * jj + 1],
+          mfma_entry<MF>(fr, a.kp.input_mode, x0 - xsr[3 * jj], x1 - xsr[3 * jj + 1],
                      x2 - xsr[3 * jj + 2], K);
           const T* f = a.Fs + 3 * ((int64_t)ns.x + jj);
           v0 += (double)(K[0] * (float)f[0] + K[1] * (float)f[1] + K[2] * (float)f[2]);
@@ -861,14 +872,18 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
 // nhuge), tier by tier from their own (each in its own large arena). Then
 // every workgroup takes the large blocks (the next nbig in the order, largest
 // first).
-template <class T, int KIND, bool MF>
+template <class T, int KIND, int MF>
 __global__ __launch_bounds__(AW_T) void k_aca_team(AcaArgs<T> a) {
   __shared__ T wl[(KIND == KIND_MLP && !MF) ? MLP_NP : 1];
-  __shared__ bf16x8 fr[MF ? FR_TOTAL : 1];
+  __shared__ bf16x8 frb[MF == MF_BF16 ? FR_TOTAL : 1];
+  __shared__ float frf[MF == MF_F32 ? F32_FRAGS * 64 : 1];
   __shared__ TeamSh<T> sh;
   __shared__ TeamRed tr;
-  if (MF) {
-    stage_frags(fr, a.frags, AW_T);
+  const void* fr = MF == MF_F32 ? (const void*)frf : (const void*)frb;
+  if (MF == MF_BF16) {
+    stage_frags(frb, a.frags, AW_T);
+  } else if (MF == MF_F32) {
+    stage_frags_f32(frf, a.frags32, AW_T);
   } else if (KIND == KIND_MLP) {
     const T* w = (const T*)a.kp.w;
     for (int i = threadIdx.x; i < MLP_NP; i += AW_T) wl[i] = w[i];
@@ -901,13 +916,17 @@ __global__ __launch_bounds__(AW_T) void k_aca_team(AcaArgs<T> a) {
 
 // Workgroups of AW waves, every wave a worker on its own small blocks
 // order[b0 + nhuge + nbig .. b1) (largest first).
-template <class T, int KIND, bool MF>
+template <class T, int KIND, int MF>
 __global__ __launch_bounds__(AW_T) void k_aca(AcaArgs<T> a) {
   __shared__ T wl[(KIND == KIND_MLP && !MF) ? MLP_NP : 1];
-  __shared__ bf16x8 fr[MF ? FR_TOTAL : 1];
+  __shared__ bf16x8 frb[MF == MF_BF16 ? FR_TOTAL : 1];
+  __shared__ float frf[MF == MF_F32 ? F32_FRAGS * 64 : 1];
   __shared__ TeamSh<T> shw[AW];
-  if (MF) {
-    stage_frags(fr, a.frags, AW_T);
+  const void* fr = MF == MF_F32 ? (const void*)frf : (const void*)frb;
+  if (MF == MF_BF16) {
+    stage_frags(frb, a.frags, AW_T);
+  } else if (MF == MF_F32) {
+    stage_frags_f32(frf, a.frags32, AW_T);
   } else if (KIND == KIND_MLP) {
     const T* w = (const T*)a.kp.w;
     for (int i = threadIdx.x; i < MLP_NP; i += AW_T) wl[i] = w[i];
@@ -956,17 +975,24 @@ void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
   a.ublk = ublk;
   a.uoff = uoff;
   a.frags = k->pbf.as<uint4>();
+  a.frags32 = k->pf32.as<float4>();
   a.det_pivot = lr->prec != HH_FP64 || k->kind == KIND_RPY6;
   const int64_t nb = b1 - b0;
   if (nb <= 0) return;
   // persistent grid: as many workgroups as stay resident, each wave a worker
-  const bool mf = k->kind == KIND_MLP && is_bf16(lr->prec);
-  const void* fn = mf ? (const void*)k_aca<float, KIND_MLP, true>
-                      : (k->kind == KIND_MLP ? (const void*)k_aca<T, KIND_MLP, false>
-                                             : (const void*)k_aca<T, KIND_RPY, false>);
-  const void* fnt = mf ? (const void*)k_aca_team<float, KIND_MLP, true>
-                       : (k->kind == KIND_MLP ? (const void*)k_aca_team<T, KIND_MLP, false>
-                                              : (const void*)k_aca_team<T, KIND_RPY, false>);
+  // the kernel MLP samples on MFMA tiles: BF16 in the BF16 forms, FP32 in the
+  // FP32 form; the FP64 form and the RPY kernels evaluate on the VALU
+  const int mfk = k->kind != KIND_MLP ? MF_NONE
+                  : is_bf16(lr->prec) ? MF_BF16
+                  : lr->prec == HH_FP32 ? MF_F32 : MF_NONE;
+  const void* fn = mfk == MF_BF16 ? (const void*)k_aca<float, KIND_MLP, MF_BF16>
+                   : mfk == MF_F32 ? (const void*)k_aca<float, KIND_MLP, MF_F32>
+                   : k->kind == KIND_MLP ? (const void*)k_aca<T, KIND_MLP, MF_NONE>
+                                         : (const void*)k_aca<T, KIND_RPY, MF_NONE>;
+  const void* fnt = mfk == MF_BF16 ? (const void*)k_aca_team<float, KIND_MLP, MF_BF16>
+                    : mfk == MF_F32 ? (const void*)k_aca_team<float, KIND_MLP, MF_F32>
+                    : k->kind == KIND_MLP ? (const void*)k_aca_team<T, KIND_MLP, MF_NONE>
+                                          : (const void*)k_aca_team<T, KIND_RPY, MF_NONE>;
   int per_cu = 0, per_cu_t = 0;
   HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, AW_T, 0));
   HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_t, fnt, AW_T, 0));
@@ -1095,12 +1121,14 @@ void launch_aca_t(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, hh_lowrank lr,
       hipLaunchKernelGGL((k_aca<T, KIND_, MF_>), dim3((unsigned)grid_w), dim3(AW_T), 0,        \
                          ctx->stream, a);                                                     \
   } while (0)
-  if (k->kind == KIND_MLP && is_bf16(lr->prec)) {
-    if constexpr (sizeof(T) == 4) LAUNCH(KIND_MLP, true);
+  if (mfk == MF_BF16) {
+    if constexpr (sizeof(T) == 4) LAUNCH(KIND_MLP, MF_BF16);
+  } else if (mfk == MF_F32) {
+    if constexpr (sizeof(T) == 4) LAUNCH(KIND_MLP, MF_F32);
   } else if (k->kind == KIND_MLP) {
-    LAUNCH(KIND_MLP, false);
+    LAUNCH(KIND_MLP, MF_NONE);
   } else {
-    LAUNCH(KIND_RPY, false);
+    LAUNCH(KIND_RPY, MF_NONE);
   }
 #undef LAUNCH
   HIP_OK(hipGetLastError());

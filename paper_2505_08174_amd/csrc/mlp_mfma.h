@@ -289,6 +289,23 @@ __device__ __forceinline__ void mlp_tile_f32(const float* __restrict__ fr, float
   o[6] = h1 ? c[2] : t2; o[7] = h1 ? c[3] : t3; o[8] = h1 ? t4 : c[4];
 }
 
+// Symmetrised kernel entry K(r) = (O + O^T)/2 / (8 pi |r|) of this lane's
+// pair from the FP32 tile, r given in FP64 and rounded to FP32 (all 64 lanes
+// call it; lanes l and l + 32 hold the same r). The ACA samples and their
+// replay both come from here, so a replay reproduces a build bit for bit.
+__device__ __forceinline__ void entry_f32tile(const float* __restrict__ fr, int mode, double dx,
+                                              double dy, double dz, float K[9]) {
+  const float rx = (float)dx, ry = (float)dy, rz = (float)dz;
+  const float rs = hh_rsqrt(rx * rx + ry * ry + rz * rz);
+  const float sc = mode == HH_MLP_INPUT_DIRECTION ? rs : 1.0f;
+  float o[9];
+  mlp_tile_f32(fr, rx * sc, ry * sc, rz * sc, o);
+  const float s = rs * (float)(1.0 / (16.0 * HH_PI));
+  K[0] = 2.0f * o[0] * s; K[1] = (o[1] + o[3]) * s; K[2] = (o[2] + o[6]) * s;
+  K[3] = K[1];            K[4] = 2.0f * o[4] * s;   K[5] = (o[5] + o[7]) * s;
+  K[6] = K[2];            K[7] = K[5];              K[8] = 2.0f * o[8] * s;
+}
+
 // Stage the FP32 fragment table (global -> LDS) by the whole workgroup.
 __device__ __forceinline__ void stage_frags_f32(float* __restrict__ lds,
                                                 const float4* __restrict__ g, int nthreads) {

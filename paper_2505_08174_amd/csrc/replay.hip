@@ -9,7 +9,8 @@
 // and the kernel parameters, which is what the backward pass differentiates
 // and what a finite-difference check of it perturbs. The arithmetic and the
 // order of every sum follow the single-wave ACA worker, so replaying a build's
-// own pivots at the same positions reproduces its factors.
+// own pivots at the same positions reproduces its factors (the FP32 form's
+// kernel-MLP samples come from the same FP32 MFMA tile as the build's).
 // One workgroup per block; the factors go to a pool laid out as in the
 // stored ACA (c_k, q_k, P_k per step).
 #include <algorithm>
@@ -17,6 +18,7 @@
 #include "api_guard.h"
 #include "devmath.h"
 #include "internal.h"
+#include "mlp_mfma.h"
 
 void lowrank_stats(hh_ctx ctx, hh_tree t, hh_part p, hh_lowrank lr, bool toff);
 void block_sizes(hh_ctx ctx, hh_tree t, hh_part p, std::vector<int32_t>& cs,
@@ -36,22 +38,61 @@ __device__ __forceinline__ void sub_mm3(T K[9], const T A[9], const T B[9]) {
       K[3 * r + cc] -= A[3 * r] * B[cc] + A[3 * r + 1] * B[3 + cc] + A[3 * r + 2] * B[6 + cc];
 }
 
-template <class T, int KIND>
+// The residual of sample K (entry of row i against the pivot column, or of the
+// pivot row against column j) written to dst.
+template <class T>
+__device__ __forceinline__ void residual_col(T rs[9], const T* __restrict__ pool,
+                                             const int64_t* __restrict__ fp, int k, int64_t i,
+                                             const T* sh, T* __restrict__ dst) {
+  for (int m = 0; m < k; ++m) {
+    T cv[9];
+    const T* cm = pool + fp[m] + 9 * i;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) cv[e] = cm[e];
+    sub_mm3<T>(rs, cv, sh + 9 * m);
+  }
+#pragma unroll
+  for (int e = 0; e < 9; ++e) dst[e] = rs[e];
+}
+
+template <class T>
+__device__ __forceinline__ void residual_row(T rs[9], const T* __restrict__ pool,
+                                             const int64_t* __restrict__ fp, int k, int64_t c,
+                                             int64_t j, const T* sh, T* __restrict__ dst) {
+  for (int m = 0; m < k; ++m) {
+    T qv[9];
+    const T* qm = pool + fp[m] + 9 * c + 9 * j;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) qv[e] = qm[e];
+    sub_mm3<T>(rs, sh + 9 * m, qv);
+  }
+#pragma unroll
+  for (int e = 0; e < 9; ++e) dst[e] = rs[e];
+}
+
+// F32T: kernel-MLP samples from the FP32 MFMA tile (the FP32 form's ACA
+// samples), each wave taking 32 rows or columns per tile.
+template <class T, int KIND, bool F32T>
 __global__ __launch_bounds__(TB) void k_aca_replay(const int2* __restrict__ G, int64_t nG,
                                                    const int4* __restrict__ nodes,
                                                    const double* __restrict__ xs, KParams kp,
+                                                   const float4* __restrict__ frags32,
                                                    const int32_t* __restrict__ rank,
                                                    int32_t* __restrict__ flag,
                                                    const int32_t* __restrict__ piv,
                                                    const int64_t* __restrict__ fptr,
                                                    T* __restrict__ pool) {
-  __shared__ T wl[KIND == KIND_MLP ? MLP_NP : 1];
+  __shared__ T wl[(KIND == KIND_MLP && !F32T) ? MLP_NP : 1];
+  __shared__ float fr[F32T ? F32_FRAGS * 64 : 1];
   __shared__ T sh[LMAX_CAP * 9];   // q_m(j_k) in the column step, c_m(i_k) in the row step
-  if (KIND == KIND_MLP) {
+  if (F32T) {
+    stage_frags_f32(fr, frags32, TB);
+  } else if (KIND == KIND_MLP) {
     const T* w = (const T*)kp.w;
     for (int i = threadIdx.x; i < MLP_NP; i += TB) wl[i] = w[i];
   }
   __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int64_t b = blockIdx.x; b < nG; b += gridDim.x) {
     const int l = rank[b];
     if (flag[b] || l == 0) continue;
@@ -73,19 +114,27 @@ __global__ __launch_bounds__(TB) void k_aca_replay(const int2* __restrict__ G, i
       }
       __syncthreads();
       const double y0 = xsr[3 * jk], y1 = xsr[3 * jk + 1], y2 = xsr[3 * jk + 2];
-      for (int i = threadIdx.x; i < c; i += TB) {
-        T rs[9];
-        kernel_entry<T>(kp, wl, (T)(xt[3 * i] - y0), (T)(xt[3 * i + 1] - y1),
-                        (T)(xt[3 * i + 2] - y2), rs, i & 1, jk & 1);
-        for (int m = 0; m < k; ++m) {
-          T cv[9];
-          const T* cm = pool + fp[m] + 9 * (int64_t)i;
+      if constexpr (F32T) {
+        for (int t0 = 32 * wv; t0 < c; t0 += 32 * (TB / 64)) {   // uniform per wave
+          const int i = t0 + (lane & 31);
+          const int ii = i < c ? i : t0;
+          float K[9];
+          entry_f32tile(fr, kp.input_mode, xt[3 * ii] - y0, xt[3 * ii + 1] - y1,
+                        xt[3 * ii + 2] - y2, K);
+          if (i < c && lane < 32) {
+            T rs[9];
 #pragma unroll
-          for (int e = 0; e < 9; ++e) cv[e] = cm[e];
-          sub_mm3<T>(rs, cv, sh + 9 * m);
+            for (int e = 0; e < 9; ++e) rs[e] = (T)K[e];
+            residual_col<T>(rs, pool, fp, k, i, sh, Ck + 9 * (int64_t)i);
+          }
         }
-#pragma unroll
-        for (int e = 0; e < 9; ++e) Ck[9 * (int64_t)i + e] = rs[e];
+      } else {
+        for (int i = threadIdx.x; i < c; i += TB) {
+          T rs[9];
+          kernel_entry<T>(kp, wl, (T)(xt[3 * i] - y0), (T)(xt[3 * i + 1] - y1),
+                          (T)(xt[3 * i + 2] - y2), rs, i & 1, jk & 1);
+          residual_col<T>(rs, pool, fp, k, i, sh, Ck + 9 * (int64_t)i);
+        }
       }
       __syncthreads();
       // pivot entry and its inverse in FP64, as in the ACA worker
@@ -139,19 +188,27 @@ __global__ __launch_bounds__(TB) void k_aca_replay(const int2* __restrict__ G, i
       }
       __syncthreads();
       const double x0 = xt[3 * ik], x1 = xt[3 * ik + 1], x2 = xt[3 * ik + 2];
-      for (int j = threadIdx.x; j < q; j += TB) {
-        T rs[9];
-        kernel_entry<T>(kp, wl, (T)(x0 - xsr[3 * j]), (T)(x1 - xsr[3 * j + 1]),
-                        (T)(x2 - xsr[3 * j + 2]), rs, ik & 1, j & 1);
-        for (int m = 0; m < k; ++m) {
-          T qv[9];
-          const T* qm = pool + fp[m] + 9 * (int64_t)c + 9 * (int64_t)j;
+      if constexpr (F32T) {
+        for (int t0 = 32 * wv; t0 < q; t0 += 32 * (TB / 64)) {   // uniform per wave
+          const int j = t0 + (lane & 31);
+          const int jj = j < q ? j : t0;
+          float K[9];
+          entry_f32tile(fr, kp.input_mode, x0 - xsr[3 * jj], x1 - xsr[3 * jj + 1],
+                        x2 - xsr[3 * jj + 2], K);
+          if (j < q && lane < 32) {
+            T rs[9];
 #pragma unroll
-          for (int e = 0; e < 9; ++e) qv[e] = qm[e];
-          sub_mm3<T>(rs, sh + 9 * m, qv);
+            for (int e = 0; e < 9; ++e) rs[e] = (T)K[e];
+            residual_row<T>(rs, pool, fp, k, c, j, sh, Qk + 9 * (int64_t)j);
+          }
         }
-#pragma unroll
-        for (int e = 0; e < 9; ++e) Qk[9 * (int64_t)j + e] = rs[e];
+      } else {
+        for (int j = threadIdx.x; j < q; j += TB) {
+          T rs[9];
+          kernel_entry<T>(kp, wl, (T)(x0 - xsr[3 * j]), (T)(x1 - xsr[3 * j + 1]),
+                          (T)(x2 - xsr[3 * j + 2]), rs, ik & 1, j & 1);
+          residual_row<T>(rs, pool, fp, k, c, j, sh, Qk + 9 * (int64_t)j);
+        }
       }
       __syncthreads();
     }
@@ -227,15 +284,17 @@ hh_lowrank_s* build_lowrank_pivots(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k
       PhaseTimer timer(ctx, HH_PHASE_ACA);
       const KParams kp = make_kparams(k, prec == HH_FP64);
       const unsigned grid = (unsigned)std::min<int64_t>(nG, 4096);
-#define REPLAY(T_, KIND_)                                                                  \
-  hipLaunchKernelGGL((k_aca_replay<T_, KIND_>), dim3(grid), dim3(TB), 0, st, p->G.as<int2>(), \
-                     nG, t->nodes.as<int4>(), t->xs.as<double>(), kp, lr->rank.as<int32_t>(),  \
-                     lr->flag.as<int32_t>(), lr->piv.as<int32_t>(), lr->fptr.as<int64_t>(),    \
-                     lr->pool.as<T_>())
+#define REPLAY(T_, KIND_, F32T_)                                                             \
+  hipLaunchKernelGGL((k_aca_replay<T_, KIND_, F32T_>), dim3(grid), dim3(TB), 0, st,           \
+                     p->G.as<int2>(), nG, t->nodes.as<int4>(), t->xs.as<double>(), kp,         \
+                     k->pf32.as<float4>(), lr->rank.as<int32_t>(), lr->flag.as<int32_t>(),    \
+                     lr->piv.as<int32_t>(), lr->fptr.as<int64_t>(), lr->pool.as<T_>())
       if (prec == HH_FP64) {
-        if (k->kind == KIND_MLP) REPLAY(double, KIND_MLP); else REPLAY(double, KIND_RPY);
+        if (k->kind == KIND_MLP) REPLAY(double, KIND_MLP, false);
+        else REPLAY(double, KIND_RPY, false);
       } else {
-        if (k->kind == KIND_MLP) REPLAY(float, KIND_MLP); else REPLAY(float, KIND_RPY);
+        if (k->kind == KIND_MLP) REPLAY(float, KIND_MLP, true);
+        else REPLAY(float, KIND_RPY, false);
       }
 #undef REPLAY
       HIP_OK(hipGetLastError());
