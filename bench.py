@@ -118,8 +118,9 @@ def stored_counters(workload):
             key = "k_near" if k.startswith("k_near") else "k_aca"
             if m.get("source_sha256_" + key) != sources_sha(key):
                 continue
+            tfs = rec.get("mfma_bf16_TFs_issued", rec.get("mfma_f32_TFs_issued", 0.0))
             out[k] = {"mfma_busy_frac": round(rec["mfma_busy_frac"], 4),
-                      "mfma_bf16_TFs_issued": round(rec["mfma_bf16_TFs_issued"], 1),
+                      "mfma_TFs_issued": round(tfs, 1),
                       "mfma_issued_frac_of_peak": round(rec["mfma_issued_frac_of_peak"], 4),
                       "source": "profiles/mlp_mfma_%s_counters.txt" % workload}
     f = _profile_json("far_apply_traffic.txt")
