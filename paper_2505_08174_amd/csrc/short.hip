@@ -15,14 +15,19 @@
 // of the (single-system) tree: particles are sorted by cell (the radix sort of
 // the tree), every particle scans the 27 cells around its own, and the
 // neighbour lists are kept in CSR form in the tree's particle order. The
-// product is one thread per target particle, over its neighbours and then its
-// 3-cliques, with both networks' weights in LDS; each thread owns its row,
-// so the sums are deterministic and need no atomics.
+// product (FP64 form) is one thread per target particle, over its neighbours
+// and then its 3-cliques, with both networks' weights in LDS. The FP32 forms
+// run both networks on FP32 MFMA tiles with one wave per target particle:
+// its neighbour pairs 32 at a time, then its 3-cliques packed 32 per tile
+// across neighbours k (a prefix sum of the degrees of up to 64 neighbours
+// maps a tile slot to its pair (k, j)). Each target's row is owned by one
+// thread or wave, so the sums are deterministic and need no atomics.
 #include <algorithm>
 
 #include "api_guard.h"
 #include "devmath.h"
 #include "internal.h"
+#include "mlp_mfma.h"
 
 // Packed parameters of g (6-64-64-64-18), each W row-major [out][in].
 #define G3_W1 0
@@ -46,6 +51,7 @@ struct hh_short_s {
   DevBuf w2_64, w2_32;     // h_s parameters (HH_MLP_NPARAM)
   DevBuf w3_64, w3_32;     // g parameters (HH_G3_NPARAM)
   DevBuf ws_f;             // forces in tree order (workspace of a product)
+  DevBuf fr_h, fr_g;       // FP32 MFMA fragment tables of h_s and g
 };
 
 namespace {
@@ -257,6 +263,128 @@ __global__ __launch_bounds__(TB) void k_short(const double* __restrict__ xs,
   U[3 * o + 2] = (TU)((double)U[3 * o + 2] + u2);
 }
 
+constexpr int SB = 512;   // eight waves per workgroup
+
+// Inclusive prefix sum over the 64 lanes.
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(v, o, 64);
+    if (lane >= o) v += u;
+  }
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Short-range terms of the FP32 forms on FP32 MFMA tiles, one wave per target
+// particle s (tree order), persistent waves with a fixed assignment.
+template <class TU>
+__global__ __launch_bounds__(SB) void k_short_f32(const double* __restrict__ xs,
+                                                  const int32_t* __restrict__ perm, int64_t n,
+                                                  const int64_t* __restrict__ ptr,
+                                                  const int32_t* __restrict__ nb,
+                                                  const float4* __restrict__ frh,
+                                                  const float4* __restrict__ frg, double inv_rc,
+                                                  const float* __restrict__ Fs,
+                                                  TU* __restrict__ U) {
+  __shared__ float fh[F32_FRAGS * 64];
+  __shared__ float fg[G32_FRAGS * 64];
+  __shared__ int pref[SB / 64][65];
+  __shared__ int kk[SB / 64][64];
+  stage_frags_f32(fh, frh, SB);
+  {
+    float4* d = reinterpret_cast<float4*>(fg);
+    for (int i = threadIdx.x; i < G32_FRAGS * 16; i += SB) d[i] = frg[i];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, p = lane & 31;
+  const bool h0 = lane < 32;
+  const int64_t wave = (int64_t)blockIdx.x * (SB / 64) + w, nw = (int64_t)gridDim.x * (SB / 64);
+  const double c8 = 1.0 / (8.0 * HH_PI);
+  for (int64_t s = wave; s < n; s += nw) {
+    const double x0 = xs[3 * s], x1 = xs[3 * s + 1], x2 = xs[3 * s + 2];
+    const float f0 = Fs[3 * s], f1 = Fs[3 * s + 1], f2 = Fs[3 * s + 2];
+    const int64_t p0 = ptr[s], p1 = ptr[s + 1];
+    double u0 = 0, u1 = 0, u2 = 0;
+    // two-body self term: sum_j alpha_2^(s)(x_j - x_i) F_i, 32 neighbours per tile
+    for (int64_t t0 = p0; t0 < p1; t0 += 32) {
+      const int64_t q = t0 + p;
+      const bool ok = q < p1;
+      const int64_t j = nb[ok ? q : p0];
+      float K[9];
+      entry_f32tile(fh, HH_MLP_INPUT_DIRECTION, xs[3 * j] - x0, xs[3 * j + 1] - x1,
+                    xs[3 * j + 2] - x2, K);
+      if (ok && h0) {
+        u0 += (double)(K[0] * f0 + K[1] * f1 + K[2] * f2);
+        u1 += (double)(K[3] * f0 + K[4] * f1 + K[5] * f2);
+        u2 += (double)(K[6] * f0 + K[7] * f1 + K[8] * f2);
+      }
+    }
+    // three-body terms over the 3-cliques (j, k, s), up to 64 neighbours k at a time
+    for (int64_t g0 = p0; g0 < p1; g0 += 64) {
+      const int64_t pk = g0 + lane;
+      const bool okk = pk < p1;
+      const int k = okk ? nb[pk] : 0;
+      const int dk = okk ? (int)(ptr[k + 1] - ptr[k]) : 0;
+      const int incl = wave_incl_scan(dk);
+      __builtin_amdgcn_wave_barrier();
+      __asm__ volatile("" ::: "memory");
+      pref[w][lane + 1] = incl;
+      kk[w][lane] = k;
+      if (lane == 0) pref[w][0] = 0;
+      const int tot = __shfl(incl, 63, 64);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      for (int t0 = 0; t0 < tot; t0 += 32) {
+        const int t1 = t0 + p;
+        const bool okt = t1 < tot;
+        const int t = okt ? t1 : 0;
+        int lo = 0, hi = 64;   // pref[lo] <= t < pref[hi]
+#pragma unroll
+        for (int it = 0; it < 6; ++it) {
+          const int mid = (lo + hi) >> 1;
+          if (pref[w][mid] <= t) lo = mid; else hi = mid;
+        }
+        const int kv = kk[w][lo];
+        const int64_t j = nb[ptr[kv] + (t - pref[w][lo])];
+        const bool valid = okt && j != s;
+        const double k0 = xs[3 * (int64_t)kv] - x0, k1 = xs[3 * (int64_t)kv + 1] - x1,
+                     k2 = xs[3 * (int64_t)kv + 2] - x2;
+        const double j0 = xs[3 * j] - x0, j1 = xs[3 * j + 1] - x1, j2 = xs[3 * j + 2] - x2;
+        const double e0 = j0 - k0, e1 = j1 - k1, e2 = j2 - k2;
+        const double rki = sqrt(k0 * k0 + k1 * k1 + k2 * k2);
+        const double rjk = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+        const float v[6] = {(float)(j0 * inv_rc), (float)(j1 * inv_rc), (float)(j2 * inv_rc),
+                            (float)(k0 * inv_rc), (float)(k1 * inv_rc), (float)(k2 * inv_rc)};
+        float o[18];
+        mlp_tile_f32_g(fg, v, o);
+        if (valid && h0) {
+          const float sc = (float)(c8 / (rjk * rki));
+          add_sym<float>(o, sc, f0, f1, f2, u0, u1, u2);
+          add_sym<float>(o + 9, sc, Fs[3 * j], Fs[3 * j + 1], Fs[3 * j + 2], u0, u1, u2);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      __builtin_amdgcn_wave_barrier();   // pref and kk are read before the next group
+    }
+    u0 = wave_sum_d(u0);
+    u1 = wave_sum_d(u1);
+    u2 = wave_sum_d(u2);
+    if (lane == 0) {
+      const int64_t o = perm[s];
+      U[3 * o] = (TU)((double)U[3 * o] + u0);
+      U[3 * o + 1] = (TU)((double)U[3 * o + 1] + u1);
+      U[3 * o + 2] = (TU)((double)U[3 * o + 2] + u2);
+    }
+  }
+}
+
 template <class T>
 void upload_params(hh_ctx ctx, DevBuf& d, const double* p, int np) {
   std::vector<T> v(p, p + np);
@@ -273,11 +401,19 @@ void short_matvec_t(hh_ctx ctx, hh_short_s* sh, const void* F, void* U) {
   sh->ws_f.ensure(st, 3 * n * sizeof(T));
   hipLaunchKernelGGL((k_gather_f<TI, T>), dim3(nblk(n)), dim3(TB), 0, st, (const TI*)F,
                      t->perm.as<int32_t>(), n, sh->ws_f.as<T>());
-  const bool fp64 = sizeof(T) == 8;
-  hipLaunchKernelGGL((k_short<T, TU>), dim3(nblk(n)), dim3(TB), 0, st, t->xs.as<double>(),
-                     t->perm.as<int32_t>(), n, sh->nb_ptr.as<int64_t>(), sh->nb.as<int32_t>(),
-                     (fp64 ? sh->w2_64 : sh->w2_32).as<T>(), (fp64 ? sh->w3_64 : sh->w3_32).as<T>(),
-                     1.0 / sh->r_cut, sh->ws_f.as<T>(), (TU*)U);
+  if constexpr (sizeof(T) == 4) {
+    const unsigned grid = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>((n + SB / 64 - 1) / (SB / 64), ctx->n_cu));
+    hipLaunchKernelGGL((k_short_f32<TU>), dim3(grid), dim3(SB), 0, st, t->xs.as<double>(),
+                       t->perm.as<int32_t>(), n, sh->nb_ptr.as<int64_t>(), sh->nb.as<int32_t>(),
+                       sh->fr_h.as<float4>(), sh->fr_g.as<float4>(), 1.0 / sh->r_cut,
+                       sh->ws_f.as<float>(), (TU*)U);
+  } else {
+    hipLaunchKernelGGL((k_short<T, TU>), dim3(nblk(n)), dim3(TB), 0, st, t->xs.as<double>(),
+                       t->perm.as<int32_t>(), n, sh->nb_ptr.as<int64_t>(), sh->nb.as<int32_t>(),
+                       sh->w2_64.as<T>(), sh->w3_64.as<T>(), 1.0 / sh->r_cut, sh->ws_f.as<T>(),
+                       (TU*)U);
+  }
   HIP_OK(hipGetLastError());
 }
 
@@ -311,6 +447,16 @@ hh_status hh_short_create(hh_ctx ctx, hh_tree tree, const double* s2_params,
     upload_params<float>(ctx, sh->w2_32, s2_params, MLP_NP);
     upload_params<double>(ctx, sh->w3_64, g3_params, G3_NP);
     upload_params<float>(ctx, sh->w3_32, g3_params, G3_NP);
+    {
+      const std::vector<float> fh = build_f32_frags(s2_params), fg = build_g32_frags(g3_params);
+      sh->fr_h.alloc(st, fh.size() * sizeof(float));
+      sh->fr_g.alloc(st, fg.size() * sizeof(float));
+      HIP_OK(hipMemcpyAsync(sh->fr_h.p, fh.data(), fh.size() * sizeof(float),
+                            hipMemcpyHostToDevice, st));
+      HIP_OK(hipMemcpyAsync(sh->fr_g.p, fg.data(), fg.size() * sizeof(float),
+                            hipMemcpyHostToDevice, st));
+      ctx_sync(ctx);   // the host tables are freed on return
+    }
     // cell grid over the root box (node 0)
     double bb[6];
     read_bytes(ctx, bb, tree->bbox.p, 6 * sizeof(double));
