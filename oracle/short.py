@@ -131,3 +131,40 @@ def short_u(X, F, hs: Net, g: Net, r_cut: float = R_CUT):
         contrib = np.einsum("pab,pb->pa", As, F[i]) + np.einsum("pab,pb->pa", At, F[j])
         np.add.at(U, i, contrib)
     return U
+
+
+def short_u_rows(X, F, hs: Net, g: Net, rows, r_cut: float = R_CUT):
+    """short_u at the particles `rows` only (for large N): N(i) of each row and
+    N(k) of each of its neighbours by the brute-force test of neighbours(),
+    one particle at a time; the cliques (j, k, i) of each row in the order of
+    cliques()."""
+    X = np.asarray(X, dtype=np.float64)
+    F = np.asarray(F, dtype=np.float64)
+    rc2 = float(r_cut) * float(r_cut)
+    cache = {}
+
+    def nb_of(i):
+        if i not in cache:
+            d = X - X[i]
+            d2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+            nb = np.nonzero(d2 < rc2)[0]
+            cache[i] = nb[nb != i]
+        return cache[i]
+
+    rows = np.asarray(rows, dtype=np.int64)
+    U = np.zeros((rows.size, 3))
+    for a, i in enumerate(rows):
+        ni = nb_of(int(i))
+        if ni.size:
+            U[a] += np.einsum("pab,b->a", alpha2_s(X[ni] - X[i], hs), F[i])
+        js, ks = [], []
+        for k in ni:
+            for j in nb_of(int(k)):
+                if j != i:
+                    js.append(j)
+                    ks.append(k)
+        if js:
+            js, ks = np.asarray(js), np.asarray(ks)
+            As, At = alpha3(X[js] - X[i], X[ks] - X[i], g, r_cut)
+            U[a] += np.einsum("pab,b->a", As, F[i]) + np.einsum("pab,pb->a", At, F[js])
+    return U

@@ -135,3 +135,15 @@ def test_networks_hand_evaluated_and_symmetric():
     A1, A2 = OS.alpha3(d, d[::-1] + 0.5, g2)
     for M in (K, A1, A2):
         assert np.allclose(M, np.swapaxes(M, 1, 2), rtol=0, atol=0)
+
+
+def test_rows_variant_equals_full():
+    # the large-N row evaluation against the full sum (same definitions,
+    # separate neighbour and clique enumeration)
+    X = wl.rsa_cube(400, 0.2, seed=31)
+    F = wl.normal_forces(400, seed=32)
+    hs, g = _seeded_nets()
+    full = OS.short_u(X, F, hs, g)
+    rows = np.array([0, 7, 123, 399])
+    got = OS.short_u_rows(X, F, hs, g, rows)
+    assert np.allclose(got, full[rows], rtol=1e-12, atol=1e-15)
