@@ -62,6 +62,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--l-max", type=int, default=48)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--graph-replays", type=int, default=0,
+                    help="batched workload: after the timed steps, time this many replays of "
+                         "the product recorded in a HIP graph (hh_batch_*) against as many "
+                         "eager products on the same structure")
     ap.add_argument("--autotune", action="store_true",
                     help="pick leaf sizes (per size class of systems) and the workgroup "
                          "threshold by timing whole steps first (not timed)")
@@ -395,6 +399,27 @@ def main():
         "roofline": roof,
         "counters": stored_counters(a.workload),
     }
+    if a.graph_replays > 0 and offsets is not None:
+        # the batched product recorded once in a HIP graph and replayed (the
+        # structure fixed); eager products on the same handle for comparison
+        b = hh.Batch(ctx, Xd, offsets, kern, c_leaf=c_leaf, eta=cfg["eta"], eps=cfg["eps"],
+                     prec=prec, l_max=a.l_max)
+        Ub = b.matvec(Fd)   # eager product, then the capture
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(a.graph_replays):
+            b.matvec(Fd, Ub)
+        torch.cuda.synchronize()
+        tg = (time.perf_counter() - tg) * 1e3 / a.graph_replays
+        te = time.perf_counter()
+        for _ in range(a.graph_replays):
+            hh.matvec(ctx, b.tree, b.part, b.lr, kern, Fd, prec)
+        torch.cuda.synchronize()
+        te = (time.perf_counter() - te) * 1e3 / a.graph_replays
+        out["batch_graph"] = {"replays": a.graph_replays, "graph_replay_ms": round(tg, 3),
+                              "eager_product_ms": round(te, 3), "graph_nodes": b.info()["graph_nodes"],
+                              "note": "product only (structure built once), not part of value"}
+        log("graph replay %.1f ms, eager product %.1f ms" % (tg, te))
     # the stored oracle rows hold the two-body product only
     gold = (golden_rows(a.workload, X, F)
             if a.n is None and offsets is None and not a.short and sus is None else None)
