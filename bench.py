@@ -34,10 +34,11 @@ PEAK = {"hbm_GBs": 8000.0, "bf16_TFs": 2500.0, "fp32_TFs": 157.3, "fp64_TFs": 78
 MLP_MAC = 3 * 64 + 64 * 64 + 64 * 64 + 64 * 9      # 8,960 multiply-adds per kernel query
 MLP_FLOP = 2 * MLP_MAC
 MLP_TANH = 3 * 64                                  # activations per kernel query
-# tanh = 1 - 2 / (2^y + 1): two transcendental ops (v_exp_f32, v_rcp_f32). On
-# gfx950 they issue at half the FP32 FMA lane rate, 32 lane-ops per clock per
-# CU (a throughput probe measured 28 for each against 57 for FMA at the clock
-# held under load), so the VALU ceiling is 16 tanh per clock per CU
+# tanh = 1 - 2 / (2^y + 1): two transcendental ops (v_exp_f32, v_rcp_f32),
+# taken at a quarter of the CU's 128 FP32 lane-ops per clock, 32 lane-ops per
+# clock per CU each, so the VALU ceiling is 16 tanh per clock per CU (the
+# near field's own counters, SQ_INSTS_VALU_TRANS_F32, show 13.9 transcendental
+# lane-ops per clock per CU at 1M)
 TANH_PER_CLK_CU = 16
 CU, CLK = 256, 2.4e9
 # sources whose change invalidates the stored HBM traffic of a kernel
