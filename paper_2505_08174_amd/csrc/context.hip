@@ -270,45 +270,6 @@ std::vector<float> build_f32_frags(const double* P0) {
   return fr;
 }
 
-// Fragment table of the three-body network on the FP32 tile (layout in
-// mlp_mfma.h: G32_*), packed parameters as HH_G3_NPARAM: W1[64][6] b1[64]
-// W2[64][64] b2[64] W3[64][64] b3[64] W4[18][64] b4[18].
-std::vector<float> build_g32_frags(const double* P0) {
-  std::vector<float> fr((size_t)G32_FRAGS * 64, 0.0f);
-  auto at = [&](int frag, int lane) -> float& { return fr[(size_t)frag * 64 + lane]; };
-  const double S = 2.0 / log(2.0);
-  const int W1 = 0, B1 = W1 + 64 * 6, W2 = B1 + 64, B2 = W2 + 64 * 64, W3 = B2 + 64,
-            B3 = W3 + 64 * 64, W4 = B3 + 64, B4 = W4 + 18 * 64;
-  auto feat = [](int mo, int r, int h) { return 32 * mo + 8 * (r / 4) + 4 * h + (r % 4); };
-  for (int mo = 0; mo < 2; ++mo)
-    for (int lane = 0; lane < 64; ++lane) {
-      const int m = 32 * mo + (lane & 31), h = lane >> 5;
-      for (int st = 0; st < 3; ++st) at(G32_L1 + 4 * mo + st, lane) = (float)(S * P0[W1 + 6 * m + 2 * st + h]);
-      at(G32_L1 + 4 * mo + 3, lane) = h == 0 ? (float)(S * P0[B1 + m]) : 0.0f;
-    }
-  auto hidden = [&](int base, int w, int b) {
-    for (int mp = 0; mp < 2; ++mp)
-      for (int lane = 0; lane < 64; ++lane) {
-        const int m = 32 * mp + (lane & 31), h = lane >> 5;
-        for (int mo = 0; mo < 2; ++mo)
-          for (int r = 0; r < 16; ++r)
-            at(base + (mp * 2 + mo) * 16 + r, lane) = (float)(S * P0[w + 64 * m + feat(mo, r, h)]);
-        at(base + 64 + mp, lane) = h == 0 ? (float)(S * P0[b + m]) : 0.0f;
-      }
-  };
-  hidden(G32_L2, W2, B2);
-  hidden(G32_L3, W3, B3);
-  for (int lane = 0; lane < 64; ++lane) {
-    const int m = lane & 31, h = lane >> 5;
-    if (m >= 18) continue;
-    for (int mo = 0; mo < 2; ++mo)
-      for (int r = 0; r < 16; ++r)
-        at(G32_L4 + mo * 16 + r, lane) = (float)P0[W4 + 64 * m + feat(mo, r, h)];
-    if (h == 0) at(G32_L4 + 32, lane) = (float)P0[B4 + m];
-  }
-  return fr;
-}
-
 // Transposed weights of the FP32 MFMA backward (layout in backward_mfma.hip),
 // unscaled: [W4^T: mo' 2][s 5], [W3^T: mo' 2][mo 2][r 16], [W2^T: same],
 // then W1 by feature [d 3][64].

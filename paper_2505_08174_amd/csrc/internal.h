@@ -258,10 +258,6 @@ void launch_near_bf16(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void*
 // sgn = -1: the transposed product sum_j K(x_j - x_i) v_j
 void launch_near_f32(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k, const void* Fs, void* Un,
                      float sgn = 1.0f);
-// FP32 MFMA fragment tables (layouts in mlp_mfma.h) of a packed two-body MLP
-// (HH_MLP_NPARAM) and of a packed three-body network (HH_G3_NPARAM).
-std::vector<float> build_f32_frags(const double* P);
-std::vector<float> build_g32_frags(const double* P);
 // FP32 MFMA back-propagation of near pairs and of the ACA samples
 // (backward_mfma.hip); slots: vjp_f32_waves(ctx) x MLP_NP doubles each.
 int64_t vjp_f32_waves(hh_ctx ctx);

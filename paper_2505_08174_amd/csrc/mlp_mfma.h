@@ -312,55 +312,3 @@ __device__ __forceinline__ void stage_frags_f32(float* __restrict__ lds,
   float4* d = reinterpret_cast<float4*>(lds);
   for (int i = threadIdx.x; i < F32_FRAGS * 16; i += nthreads) d[i] = g[i];
 }
-
-// ------------------------------------------- FP32 tile of the three-body net
-//
-// The network 6 -> 64 -> 64 -> 64 -> 18 on the same FP32 tile: layer 1
-// contracts (v0, v1), (v2, v3), (v4, v5) and (1, 0) (the bias), the hidden
-// layers are those of the two-body tile (same table layout), and the output
-// layer has 18 rows of one M tile. Layers 1-3 scaled by 2 log2(e).
-#define G32_L1 0                               // [mo 2][step 4]
-#define G32_L2 (G32_L1 + 8)
-#define G32_L3 (G32_L2 + 66)
-#define G32_L4 (G32_L3 + 66)                   // [mo 2][r 16], bias
-#define G32_FRAGS (G32_L4 + 33)
-
-// Raw outputs o[0..17] of the three-body network at input v[6] for this
-// lane's pair (all 64 lanes; lanes l and l + 32 hold the same input).
-__device__ __forceinline__ void mlp_tile_f32_g(const float* __restrict__ fr, const float (&v)[6],
-                                               float (&o)[18]) {
-  __asm__ volatile("" ::: "memory");
-  const int lane = threadIdx.x & 63;
-  const bool h1 = lane >= 32;
-  const float bone = h1 ? 0.0f : 1.0f;
-  float h[2][16], g[2][16];
-  {
-    const float b[4] = {h1 ? v[1] : v[0], h1 ? v[3] : v[2], h1 ? v[5] : v[4], bone};
-#pragma unroll
-    for (int mo = 0; mo < 2; ++mo) {
-      f32x16 a = f32x16{};
-#pragma unroll
-      for (int st = 0; st < 4; ++st) a = mfma_f32(fr[(G32_L1 + 4 * mo + st) * 64 + lane], b[st], a);
-#pragma unroll
-      for (int r = 0; r < 16; ++r) h[mo][r] = tanh_scaled(a[r]);
-    }
-  }
-  hidden_f32(fr, G32_L2, lane, bone, h, g);
-  hidden_f32(fr, G32_L3, lane, bone, g, h);
-  f32x16 c0 = mfma_f32(fr[(G32_L4 + 32) * 64 + lane], bone, f32x16{});
-  f32x16 c1 = f32x16{};
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    c0 = mfma_f32(fr[(G32_L4 + r) * 64 + lane], h[0][r], c0);
-    c1 = mfma_f32(fr[(G32_L4 + 16 + r) * 64 + lane], h[1][r], c1);
-  }
-  // row 8 (r / 4) + 4 h + r % 4 of register r: rows 0-17 sit in registers 0-9
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const float mine = c0[r] + c1[r];
-    const float other = __shfl_xor(mine, 32, 64);
-    const int lo = 8 * (r / 4) + (r % 4), hi = lo + 4;
-    if (lo < 18) o[lo] = h1 ? other : mine;
-    if (hi < 18) o[hi] = h1 ? mine : other;
-  }
-}

@@ -29,6 +29,10 @@
 #include "internal.h"
 #include "mlp_mfma.h"
 
+// FP32 MFMA fragment table (layout in mlp_mfma.h) of a packed two-body MLP
+// (HH_MLP_NPARAM), context.hip.
+std::vector<float> build_f32_frags(const double* P);
+
 // Packed parameters of g (6-64-64-64-18), each W row-major [out][in].
 #define G3_W1 0
 #define G3_B1 (G3_W1 + MLP_H * 6)
@@ -40,6 +44,95 @@
 #define G3_B4 (G3_W4 + 18 * MLP_H)
 #define G3_NP (G3_B4 + 18)
 static_assert(G3_NP == HH_G3_NPARAM, "packed layout of the three-body network");
+
+// The three-body network on the FP32 tile of mlp_mfma.h: the network 6 -> 64 -> 64 -> 64 -> 18 on the same FP32 tile: layer 1
+// contracts (v0, v1), (v2, v3), (v4, v5) and (1, 0) (the bias), the hidden
+// layers are those of the two-body tile (same table layout), and the output
+// layer has 18 rows of one M tile. Layers 1-3 scaled by 2 log2(e).
+#define G32_L1 0                               // [mo 2][step 4]
+#define G32_L2 (G32_L1 + 8)
+#define G32_L3 (G32_L2 + 66)
+#define G32_L4 (G32_L3 + 66)                   // [mo 2][r 16], bias
+#define G32_FRAGS (G32_L4 + 33)
+
+// Raw outputs o[0..17] of the three-body network at input v[6] for this
+// lane's pair (all 64 lanes; lanes l and l + 32 hold the same input).
+__device__ __forceinline__ void mlp_tile_f32_g(const float* __restrict__ fr, const float (&v)[6],
+                                               float (&o)[18]) {
+  __asm__ volatile("" ::: "memory");
+  const int lane = threadIdx.x & 63;
+  const bool h1 = lane >= 32;
+  const float bone = h1 ? 0.0f : 1.0f;
+  float h[2][16], g[2][16];
+  {
+    const float b[4] = {h1 ? v[1] : v[0], h1 ? v[3] : v[2], h1 ? v[5] : v[4], bone};
+#pragma unroll
+    for (int mo = 0; mo < 2; ++mo) {
+      f32x16 a = f32x16{};
+#pragma unroll
+      for (int st = 0; st < 4; ++st) a = mfma_f32(fr[(G32_L1 + 4 * mo + st) * 64 + lane], b[st], a);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) h[mo][r] = tanh_scaled(a[r]);
+    }
+  }
+  hidden_f32(fr, G32_L2, lane, bone, h, g);
+  hidden_f32(fr, G32_L3, lane, bone, g, h);
+  f32x16 c0 = mfma_f32(fr[(G32_L4 + 32) * 64 + lane], bone, f32x16{});
+  f32x16 c1 = f32x16{};
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    c0 = mfma_f32(fr[(G32_L4 + r) * 64 + lane], h[0][r], c0);
+    c1 = mfma_f32(fr[(G32_L4 + 16 + r) * 64 + lane], h[1][r], c1);
+  }
+  // row 8 (r / 4) + 4 h + r % 4 of register r: rows 0-17 sit in registers 0-9
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const float mine = c0[r] + c1[r];
+    const float other = __shfl_xor(mine, 32, 64);
+    const int lo = 8 * (r / 4) + (r % 4), hi = lo + 4;
+    if (lo < 18) o[lo] = h1 ? other : mine;
+    if (hi < 18) o[hi] = h1 ? mine : other;
+  }
+}
+
+// Fragment table of the three-body network on the FP32 tile (layout in
+// mlp_mfma.h: G32_*), packed parameters as HH_G3_NPARAM: W1[64][6] b1[64]
+// W2[64][64] b2[64] W3[64][64] b3[64] W4[18][64] b4[18].
+static std::vector<float> build_g32_frags(const double* P0) {
+  std::vector<float> fr((size_t)G32_FRAGS * 64, 0.0f);
+  auto at = [&](int frag, int lane) -> float& { return fr[(size_t)frag * 64 + lane]; };
+  const double S = 2.0 / log(2.0);
+  const int W1 = 0, B1 = W1 + 64 * 6, W2 = B1 + 64, B2 = W2 + 64 * 64, W3 = B2 + 64,
+            B3 = W3 + 64 * 64, W4 = B3 + 64, B4 = W4 + 18 * 64;
+  auto feat = [](int mo, int r, int h) { return 32 * mo + 8 * (r / 4) + 4 * h + (r % 4); };
+  for (int mo = 0; mo < 2; ++mo)
+    for (int lane = 0; lane < 64; ++lane) {
+      const int m = 32 * mo + (lane & 31), h = lane >> 5;
+      for (int st = 0; st < 3; ++st) at(G32_L1 + 4 * mo + st, lane) = (float)(S * P0[W1 + 6 * m + 2 * st + h]);
+      at(G32_L1 + 4 * mo + 3, lane) = h == 0 ? (float)(S * P0[B1 + m]) : 0.0f;
+    }
+  auto hidden = [&](int base, int w, int b) {
+    for (int mp = 0; mp < 2; ++mp)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int m = 32 * mp + (lane & 31), h = lane >> 5;
+        for (int mo = 0; mo < 2; ++mo)
+          for (int r = 0; r < 16; ++r)
+            at(base + (mp * 2 + mo) * 16 + r, lane) = (float)(S * P0[w + 64 * m + feat(mo, r, h)]);
+        at(base + 64 + mp, lane) = h == 0 ? (float)(S * P0[b + m]) : 0.0f;
+      }
+  };
+  hidden(G32_L2, W2, B2);
+  hidden(G32_L3, W3, B3);
+  for (int lane = 0; lane < 64; ++lane) {
+    const int m = lane & 31, h = lane >> 5;
+    if (m >= 18) continue;
+    for (int mo = 0; mo < 2; ++mo)
+      for (int r = 0; r < 16; ++r)
+        at(G32_L4 + mo * 16 + r, lane) = (float)P0[W4 + 64 * m + feat(mo, r, h)];
+    if (h == 0) at(G32_L4 + 32, lane) = (float)P0[B4 + m];
+  }
+  return fr;
+}
 
 struct hh_short_s {
   hh_ctx ctx = nullptr;
