@@ -213,3 +213,18 @@ def test_refusals():
     s2, g3 = wl.mlp_weights(11), wl.mlp_weights(12, widths=(6, 64, 64, 64, 18))
     with pytest.raises(hh.HHError, match="particles"):
         hh.ShortRange(ctx(), t6, s2, g3, 5.0)
+
+
+def test_edge_sizes():
+    """1, 2, 5 and 65 particles (a single leaf, ragged leaves): the 6N product
+    against the dense 6N sum, FP64."""
+    from gpu_common import ctx, dev, say
+    k6 = hh.Kernel.rpy6(ctx())
+    for n in (1, 2, 5, 65):
+        X, F, T = _case(n, seed=19 + n, phi=0.05)
+        say("6N edge", n)
+        hm = hh.HMatrix(ctx(), dev(X), k6, c_leaf=4, eps=1e-8, prec="fp64")
+        Y = (hm @ _g6(F, T)).cpu().numpy()
+        ref = _ref(X, F, T)
+        assert Y.shape == (n, 6)
+        assert _rel(Y, ref) < 1e-6 and _row(Y, ref) < 1e-6
