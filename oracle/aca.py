@@ -30,14 +30,25 @@ Readings where the paper is silent or inconsistent (listed in the design notes):
     min(c, q) terms interpolates every row or column and counts as converged;
   * guards: a residual column whose largest entry has ||a||^2 <= 1e-30 lambda^2
     ends the iteration as converged without a new term; a pivot entry with
-    |det P| <= 1e-14 ||P||_F^3 ends it with a dense fallback.
+    |det P| <= s ||P||_F^3 ends it with a dense fallback, s = 1e-14 under the
+    Frobenius rule (a singularity guard only: Algorithm 2 screens pivots by
+    size, not by conditioning) and s = 1e-8 under the determinant rule. For a
+    3x3 matrix |det P| = s1 s2 s3 <= s1^2 s3, so the 2-norm condition number
+    obeys s1 / s3 <= ||P||_F^3 / |det P|. The determinant rule takes the best
+    conditioned entry of the column it can find; when even that one has a
+    condition number above 1e8 the column holds no usable pivot, and inverting
+    it would carry FP64 rounding into c_k = a P^-1 beyond 1e-8 relative. On
+    the 6N grid, whose coupling entries are singular, such pivots follow a
+    step that grew the residual 1e4-fold, and the block's result then depends
+    on the rounding of the inverse at the 1e-6 level.
 """
 from __future__ import annotations
 
 import numpy as np
 
 TINY = 1e-30
-SING = 1e-14
+SING = 1e-14       # Frobenius rule
+SING_DET = 1e-8    # determinant rule
 
 
 class ACAResult:
@@ -95,7 +106,7 @@ def aca_entries(col, row, c: int, q: int, eps: float, l_max: int,
         ik = int(np.argmax(np.where(used_i, -1.0, _magnitude(a, pivot))))
         P = a[ik]
         fro = np.sqrt(np.sum(P * P))
-        if abs(np.linalg.det(P)) <= SING * fro ** 3:
+        if abs(np.linalg.det(P)) <= (SING_DET if pivot == "determinant" else SING) * fro ** 3:
             break
         # normalise by the pivot entry
         ck = a @ np.linalg.inv(P)

@@ -18,7 +18,11 @@
 // takes |det| in every form: its translation-rotation entries are singular
 // (antisymmetric 3x3), and the Frobenius rule would pick them as pivots.
 // Guards: a residual column with ||a||^2 <= 1e-30 lambda^2 ends as converged
-// without a new term; |det P| <= 1e-14 ||P||_F^3 ends with a dense fallback;
+// without a new term; |det P| <= s ||P||_F^3 ends with a dense fallback, with
+// s = 1e-14 under the Frobenius rule (a singularity guard) and s = 1e-8 under
+// the |det| rule: ||P||_F^3 / |det P| bounds the 2-norm condition number of a
+// 3x3 P, and when the best-conditioned entry of the column exceeds 1e8 the
+// inverse would carry FP64 rounding into c_k beyond 1e-8 relative;
 // l_max terms without convergence end with a dense fallback.
 // Factors c_k (c entries) and q_k (q entries), 9 values each, are stored
 // contiguously per step in a pool, followed by the pivot entry P_k (9 values);
@@ -592,7 +596,8 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
       double fro2 = 0;
 #pragma unroll
       for (int e = 0; e < 9; ++e) fro2 += P[e] * P[e];
-      if (!(fabs(det) > 1e-14 * fro2 * sqrt(fro2))) { fallback = true; break; }
+      const double sing = a.det_pivot ? 1e-8 : 1e-14;
+      if (!(fabs(det) > sing * fro2 * sqrt(fro2))) { fallback = true; break; }
       const double id = 1.0 / det;
       double Pi[9];
       Pi[0] = (P[4] * P[8] - P[5] * P[7]) * id;

@@ -81,7 +81,7 @@ __global__ __launch_bounds__(TB) void k_aca_replay(const int2* __restrict__ G, i
                                                    int32_t* __restrict__ flag,
                                                    const int32_t* __restrict__ piv,
                                                    const int64_t* __restrict__ fptr,
-                                                   T* __restrict__ pool) {
+                                                   T* __restrict__ pool, double sing) {
   __shared__ T wl[(KIND == KIND_MLP && !F32T) ? MLP_NP : 1];
   __shared__ float fr[F32T ? F32_FRAGS * 64 : 1];
   __shared__ T sh[LMAX_CAP * 9];   // q_m(j_k) in the column step, c_m(i_k) in the row step
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(TB) void k_aca_replay(const int2* __restrict__ G, i
       double fro2 = 0;
 #pragma unroll
       for (int e = 0; e < 9; ++e) fro2 += P[e] * P[e];
-      if (!(fabs(det) > 1e-14 * fro2 * sqrt(fro2))) {
+      if (!(fabs(det) > sing * fro2 * sqrt(fro2))) {
         // a pivot that has become singular at these positions: the block is
         // evaluated densely (uniform decision: every thread has the same P)
         if (threadIdx.x == 0) flag[b] = 1;
@@ -283,12 +283,14 @@ hh_lowrank_s* build_lowrank_pivots(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k
     if (nG > 0) {
       PhaseTimer timer(ctx, HH_PHASE_ACA);
       const KParams kp = make_kparams(k, prec == HH_FP64);
+      // the singularity guard of the pivot rule the build used
+      const double sing = (prec != HH_FP64 || k->kind == KIND_RPY6) ? 1e-8 : 1e-14;
       const unsigned grid = (unsigned)std::min<int64_t>(nG, 4096);
 #define REPLAY(T_, KIND_, F32T_)                                                             \
   hipLaunchKernelGGL((k_aca_replay<T_, KIND_, F32T_>), dim3(grid), dim3(TB), 0, st,           \
                      p->G.as<int2>(), nG, t->nodes.as<int4>(), t->xs.as<double>(), kp,         \
                      k->pf32.as<float4>(), lr->rank.as<int32_t>(), lr->flag.as<int32_t>(),    \
-                     lr->piv.as<int32_t>(), lr->fptr.as<int64_t>(), lr->pool.as<T_>())
+                     lr->piv.as<int32_t>(), lr->fptr.as<int64_t>(), lr->pool.as<T_>(), sing)
       if (prec == HH_FP64) {
         if (k->kind == KIND_MLP) REPLAY(double, KIND_MLP, false);
         else REPLAY(double, KIND_RPY, false);
