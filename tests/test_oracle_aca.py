@@ -4,7 +4,10 @@ A block that is exactly a sum of r separable 3x3 terms is recovered with rank
 r; with zero tolerance ACA interpolates the full block; after every step the
 residual vanishes on the chosen rows and columns; the incremental nu^2 and
 lambda^2 equal brute-force Frobenius norms; on admissible RPY and MLP blocks
-the block error stays within 10 zeta.
+the block error stays within 10 zeta. The pivot guard: the 2-norm condition
+number of a 3x3 entry is at most ||P||_F^3 / |det P|, and the determinant rule
+refuses a column whose entries are all conditioned worse than 1e8 (the
+Frobenius rule only refuses singular entries).
 """
 import numpy as np
 import pytest
@@ -99,3 +102,33 @@ def test_determinant_pivot_prefers_well_conditioned_entries():
     rd = aca.aca_entries(lambda j: G[:, j], lambda i: G[i, :], 2, 2, 0.0, 1, pivot="determinant")
     assert rd.rank == 1 and rd.piv_i[0] == 1
     assert rf.rank == 0 or rf.piv_i[0] == 0
+
+
+def test_condition_bound_of_the_pivot_guard():
+    # for a 3x3 matrix |det P| = s1 s2 s3 <= s1^2 s3, so the 2-norm condition
+    # number never exceeds ||P||_F^3 / |det P| (the quantity the guard caps)
+    rng = np.random.default_rng(4)
+    for scale in (1.0, 1e-3, 1e-6, 1e-9):
+        for _ in range(200):
+            U, _, Vt = np.linalg.svd(rng.normal(size=(3, 3)))
+            s = np.sort(rng.uniform(0.1, 10.0, 3))[::-1] * np.array([1.0, 1.0, scale])
+            P = U @ np.diag(s) @ Vt
+            assert np.linalg.cond(P) <= np.linalg.norm(P) ** 3 / abs(np.linalg.det(P)) * (1 + 1e-9)
+
+
+@pytest.mark.parametrize("small,usable", [(1e-9, False), (1e-6, True)])
+def test_determinant_rule_refuses_ill_conditioned_columns(small, usable):
+    # every entry of the first column has condition number 1 / small: under the
+    # determinant rule a column whose best entry is conditioned worse than 1e8
+    # holds no usable pivot (dense fallback); the Frobenius rule only refuses
+    # singular entries
+    D = np.diag([1.0, 1.0, small])
+    G = np.stack([np.stack([D, np.eye(3)]), np.stack([2.0 * D, 3.0 * np.eye(3)])])   # [2, 2, 3, 3]
+    col, row = (lambda j: G[:, j]), (lambda i: G[i, :])
+    rd = aca.aca_entries(col, row, 2, 2, 0.0, 2, piv_j1=0, pivot="determinant")
+    rf = aca.aca_entries(col, row, 2, 2, 0.0, 2, piv_j1=0, pivot="frobenius")
+    assert rf.rank >= 1
+    if usable:
+        assert rd.rank >= 1
+    else:
+        assert rd.rank == 0 and not rd.converged

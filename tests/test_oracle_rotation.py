@@ -7,7 +7,11 @@
 * M^tr T is the rotlet flow itself at the target;
 * the 6N matrix is symmetric (M^tr_ij = (M^rt_ji)^T) and positive definite for
   non-overlapping spheres;
-* the cross-product matrix and the self mobilities.
+* the cross-product matrix and the self mobilities;
+* the 6N H-matrix: dense mode is the 6N matrix, the translation block is the
+  3N RPY product, Eq. (11) holds, and with two-particle leaves (where columns
+  of singular coupling entries leave only poorly conditioned pivots) the
+  product is the dense sum to rounding.
 """
 import math
 
@@ -118,3 +122,23 @@ def test_hmatrix6_within_eq11_bound():
     ref = np.concatenate([U.ravel(), W.ravel()])
     e = np.linalg.norm(np.concatenate([Uh.ravel(), Wh.ravel()]) - ref) / np.linalg.norm(ref)
     assert e < 1e-5
+
+
+def test_hmatrix6_small_leaves_no_ill_conditioned_pivots():
+    # 65 particles in 4-row leaves (two particles): blocks small enough that a
+    # column of coupling entries (singular) leaves only poorly conditioned
+    # pivots. With the determinant rule's conditioning cap those blocks are
+    # evaluated densely and the product is the dense sum to rounding; a cap at
+    # the bare singularity level (1e-14) gave 2.5e-9 here, and 5e-7 with the
+    # inverse taken through the adjugate instead of LU
+    n = 65
+    X = wl.rsa_cube(n, 0.05, seed=84)
+    F = wl.normal_forces(n, seed=85)
+    T = wl.normal_forces(n, seed=86)
+    U, W = OR.u6(X, F, T)
+    ref = np.hstack([U, W])
+    o = OR.build6(X, 4, 1.0, 1e-8, 48)
+    Uo, Wo = OR.apply6(o, X, F, T)
+    Y = np.hstack([Uo, Wo])
+    assert np.linalg.norm(Y - ref) / np.linalg.norm(ref) < 1e-10
+    assert np.max(np.linalg.norm(Y - ref, axis=1)) / np.max(np.linalg.norm(ref, axis=1)) < 1e-10
