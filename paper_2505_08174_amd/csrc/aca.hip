@@ -22,7 +22,12 @@
 // s = 1e-14 under the Frobenius rule (a singularity guard) and s = 1e-8 under
 // the |det| rule: ||P||_F^3 / |det P| bounds the 2-norm condition number of a
 // 3x3 P, and when the best-conditioned entry of the column exceeds 1e8 the
-// inverse would carry FP64 rounding into c_k beyond 1e-8 relative;
+// inverse would carry FP64 rounding into c_k beyond 1e-8 relative. With FP32
+// residuals (the FP32 and BF16 forms) s = 1e-6, about 16 units of FP32
+// roundoff: a residual entry that is singular in exact arithmetic (the 6N
+// grid's coupling entries and their Schur complements) comes out of FP32
+// arithmetic with |det P| / ||P||_F^3 near the roundoff, and inverting it
+// would fill c_k with rounding noise;
 // l_max terms without convergence end with a dense fallback.
 // Factors c_k (c entries) and q_k (q entries), 9 values each, are stored
 // contiguously per step in a pool, followed by the pivot entry P_k (9 values);
@@ -596,7 +601,7 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
       double fro2 = 0;
 #pragma unroll
       for (int e = 0; e < 9; ++e) fro2 += P[e] * P[e];
-      const double sing = a.det_pivot ? 1e-8 : 1e-14;
+      const double sing = !a.det_pivot ? 1e-14 : sizeof(T) == 4 ? 1e-6 : 1e-8;
       if (!(fabs(det) > sing * fro2 * sqrt(fro2))) { fallback = true; break; }
       const double id = 1.0 / det;
       double Pi[9];

@@ -283,8 +283,8 @@ hh_lowrank_s* build_lowrank_pivots(hh_ctx ctx, hh_tree t, hh_part p, hh_kernel k
     if (nG > 0) {
       PhaseTimer timer(ctx, HH_PHASE_ACA);
       const KParams kp = make_kparams(k, prec == HH_FP64);
-      // the singularity guard of the pivot rule the build used
-      const double sing = (prec != HH_FP64 || k->kind == KIND_RPY6) ? 1e-8 : 1e-14;
+      // the singularity guard of the pivot rule and working type the build used
+      const double sing = prec != HH_FP64 ? 1e-6 : k->kind == KIND_RPY6 ? 1e-8 : 1e-14;
       const unsigned grid = (unsigned)std::min<int64_t>(nG, 4096);
 #define REPLAY(T_, KIND_, F32T_)                                                             \
   hipLaunchKernelGGL((k_aca_replay<T_, KIND_, F32T_>), dim3(grid), dim3(TB), 0, st,           \
