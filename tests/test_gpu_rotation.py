@@ -228,7 +228,8 @@ def test_edge_sizes(prec, eps, tol, row_tol):
     and three particles the entries' scales 1/d, 1/d^2 and 1/d^3 let the |det|
     pivots grow the residual about 100-fold before a pivot of condition number
     near 3e5, which carries FP32 roundoff (6e-8) into that block at up to 2e-3
-    (measured worst row 1.6e-4 at 65 particles; FP64 on the same blocks 7e-12)."""
+    (measured worst row 1.6e-4 at 65 particles and 3.4e-4 at 400; FP64 on the
+    same blocks 7e-12)."""
     from gpu_common import ctx, dev, say
     k6 = hh.Kernel.rpy6(ctx())
     dt = torch.float64 if prec == "fp64" else torch.float32
