@@ -652,22 +652,20 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
 #pragma unroll
         for (int e = 0; e < 9; ++e) d[e] = Akk[e];
       }
-      // normalisation: c_k = a P^-1
-      T pt[9];
-#pragma unroll
-      for (int e = 0; e < 9; ++e) pt[e] = (T)Pi[e];
+      // normalisation: c_k = a P^-1 in FP64, rounded to T once (P^-1 rounded
+      // to single precision first would carry its rounding into c_k times the
+      // condition number of P)
 #pragma unroll 1
       for (int i = tid; i < c; i += stride) {
-        T v[9], o[9];
+        double v[9];
 #pragma unroll
-        for (int e = 0; e < 9; ++e) v[e] = Ck[9 * (int64_t)i + e];
+        for (int e = 0; e < 9; ++e) v[e] = (double)Ck[9 * (int64_t)i + e];
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
           for (int cc = 0; cc < 3; ++cc)
-            o[3 * r + cc] = v[3 * r] * pt[cc] + v[3 * r + 1] * pt[3 + cc] + v[3 * r + 2] * pt[6 + cc];
-#pragma unroll
-        for (int e = 0; e < 9; ++e) Ck[9 * (int64_t)i + e] = o[e];
+            Ck[9 * (int64_t)i + 3 * r + cc] =
+                (T)(v[3 * r] * Pi[cc] + v[3 * r + 1] * Pi[3 + cc] + v[3 * r + 2] * Pi[6 + cc]);
       }
       team_sync<TW>();   // A side done with sh.qc; c_k written
 #pragma unroll 1

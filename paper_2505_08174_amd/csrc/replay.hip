@@ -159,27 +159,27 @@ __global__ __launch_bounds__(TB) void k_aca_replay(const int2* __restrict__ G, i
         break;
       }
       const double id = 1.0 / det;
-      T pt[9];
-      pt[0] = (T)((P[4] * P[8] - P[5] * P[7]) * id);
-      pt[1] = (T)((P[2] * P[7] - P[1] * P[8]) * id);
-      pt[2] = (T)((P[1] * P[5] - P[2] * P[4]) * id);
-      pt[3] = (T)((P[5] * P[6] - P[3] * P[8]) * id);
-      pt[4] = (T)((P[0] * P[8] - P[2] * P[6]) * id);
-      pt[5] = (T)((P[2] * P[3] - P[0] * P[5]) * id);
-      pt[6] = (T)((P[3] * P[7] - P[4] * P[6]) * id);
-      pt[7] = (T)((P[1] * P[6] - P[0] * P[7]) * id);
-      pt[8] = (T)((P[0] * P[4] - P[1] * P[3]) * id);
+      double Pi[9];
+      Pi[0] = (P[4] * P[8] - P[5] * P[7]) * id;
+      Pi[1] = (P[2] * P[7] - P[1] * P[8]) * id;
+      Pi[2] = (P[1] * P[5] - P[2] * P[4]) * id;
+      Pi[3] = (P[5] * P[6] - P[3] * P[8]) * id;
+      Pi[4] = (P[0] * P[8] - P[2] * P[6]) * id;
+      Pi[5] = (P[2] * P[3] - P[0] * P[5]) * id;
+      Pi[6] = (P[3] * P[7] - P[4] * P[6]) * id;
+      Pi[7] = (P[1] * P[6] - P[0] * P[7]) * id;
+      Pi[8] = (P[0] * P[4] - P[1] * P[3]) * id;
+      // c_k = a P^-1 in FP64, rounded to T once, as in the ACA worker
       for (int i = threadIdx.x; i < c; i += TB) {
-        T v[9], o[9];
+        double v[9];
 #pragma unroll
-        for (int e = 0; e < 9; ++e) v[e] = Ck[9 * (int64_t)i + e];
+        for (int e = 0; e < 9; ++e) v[e] = (double)Ck[9 * (int64_t)i + e];
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
           for (int cc = 0; cc < 3; ++cc)
-            o[3 * r + cc] = v[3 * r] * pt[cc] + v[3 * r + 1] * pt[3 + cc] + v[3 * r + 2] * pt[6 + cc];
-#pragma unroll
-        for (int e = 0; e < 9; ++e) Ck[9 * (int64_t)i + e] = o[e];
+            Ck[9 * (int64_t)i + 3 * r + cc] =
+                (T)(v[3 * r] * Pi[cc] + v[3 * r + 1] * Pi[3 + cc] + v[3 * r + 2] * Pi[6 + cc]);
       }
       __syncthreads();
       for (int t = threadIdx.x; t < 9 * k; t += TB) {
