@@ -33,9 +33,11 @@
 // contiguously per step in a pool, followed by the pivot entry P_k (9 values);
 // each step bump-allocates 9 (c + q + 1) values. In streamed mode the factors
 // of a step take 9 (c + q) values of the worker's arena.
-// Samples, residuals and factors are in the working type T; pivots, norms
-// and Gram matrices in FP64 in every form. In the BF16 form the samples come
-// from the MFMA MLP tile (activations carried as BF16 hi + lo).
+// Samples, residuals and factors are in the working type T; pivots, norms,
+// the normalisation and Gram matrices in FP64 in every form (a lane's
+// two-row share of Ghat_m is formed in T before the FP64 wave sum). In the
+// BF16 form the samples come from the MFMA MLP tile (activations carried as
+// BF16 hi + lo).
 #include <algorithm>
 #include <iterator>
 
@@ -517,7 +519,9 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
           T qv[9];
 #pragma unroll
           for (int e = 0; e < 9; ++e) qv[e] = sh.qc[9 * m + e];
-          double p[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+          // this lane's rows of c_m(i)^T r_m(i): products of the working type
+          // (FP32 in the single-precision forms), summed over the wave in FP64
+          T pl[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
           for (int r = 0; r < RCH; ++r) {
             const int i = base + 64 * r + lane;
@@ -526,9 +530,7 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
             for (int x = 0; x < 3; ++x)
 #pragma unroll
               for (int y = 0; y < 3; ++y)
-                p[3 * x + y] += (double)cv[x] * (double)rs[r][y] +
-                                (double)cv[3 + x] * (double)rs[r][3 + y] +
-                                (double)cv[6 + x] * (double)rs[r][6 + y];
+                pl[3 * x + y] += cv[x] * rs[r][y] + cv[3 + x] * rs[r][3 + y] + cv[6 + x] * rs[r][6 + y];
             sub_mm<T>(rs[r], cv, qv);
             if (fuse && m == k - 1 && i < c) {
               ub[3 * i] += (double)cv[0] * tp0 + (double)cv[1] * tp1 + (double)cv[2] * tp2;
@@ -536,6 +538,9 @@ __device__ __forceinline__ void aca_worker(const AcaArgs<T>& a, const T* wl, con
               ub[3 * i + 2] += (double)cv[6] * tp0 + (double)cv[7] * tp1 + (double)cv[8] * tp2;
             }
           }
+          double p[9];
+#pragma unroll
+          for (int e = 0; e < 9; ++e) p[e] = (double)pl[e];
           wave_sumv(p);
           if (lane == m) {
 #pragma unroll
